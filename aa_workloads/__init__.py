@@ -1,0 +1,162 @@
+"""Seeded synthetic inputs for the Anderson-acceleration workloads.
+
+This module is the only code shared by the FP64 CPU oracle (``oracle/``) and
+the HIP library (``paper_2110_09667_amd/``).  It holds the random-number
+generator and the workload recipes (grid sizes, spacing, relaxation weight,
+right-hand sides); it holds none of the arithmetic of Anderson acceleration,
+Gram-Schmidt or Givens rotations.
+
+Generator
+---------
+Every stream is counter based.  Element ``i`` of stream ``(seed, stream)`` is
+
+    u_i = (mix(base + i) >> 11) * 2**-53,      base = mix(mix(seed) + stream)
+
+where ``mix(z)`` is the output function of SplitMix64 (Steele, Lea and Flood,
+"Fast splittable pseudorandom number generators", OOPSLA 2014) applied to
+``z + 0x9E3779B97F4A7C15`` (all arithmetic modulo 2**64).  ``u_i`` lies in
+[0, 1).  Normal deviates use the Box-Muller cosine branch on the pair
+(u_{2i}, u_{2i+1}):  z_i = sqrt(-2 log(1 - u_{2i})) * cos(2 pi u_{2i+1}).
+
+The HIP library carries its own implementation of the same definition for
+inputs too large to generate on the host; uniforms agree bit for bit, normals
+agree to a few ulps (the transcendental functions differ).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+_TWO_M53 = 2.0 ** -53
+
+
+def mix(z):
+    """SplitMix64 output function of ``z + golden`` (uint64, wraps mod 2**64)."""
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = z + GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def stream_base(seed: int, stream: int) -> int:
+    """64-bit counter origin of stream ``(seed, stream)``."""
+    s = int(mix(np.uint64(seed % 2**64)))
+    return int(mix(np.uint64((s + stream) % 2**64)))
+
+
+def uniform(seed: int, stream: int, n: int, offset: int = 0) -> np.ndarray:
+    """``n`` uniforms in [0, 1) from elements ``offset .. offset+n-1``."""
+    base = stream_base(seed, stream)
+    ctr = np.arange(offset, offset + n, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        ctr = ctr + np.uint64(base)
+    return (mix(ctr) >> np.uint64(11)).astype(np.float64) * _TWO_M53
+
+
+def normal(seed: int, stream: int, n: int, offset: int = 0) -> np.ndarray:
+    """``n`` standard normals (Box-Muller, cosine branch)."""
+    u = uniform(seed, stream, 2 * n, 2 * offset)
+    u1, u2 = u[0::2], u[1::2]
+    return np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * math.pi * u2)
+
+
+# --------------------------------------------------------------------------
+# Model problems: G(u) = u - omega * (A u + c u^3 - f) on a d-dimensional
+# Dirichlet grid of s points per side, A the standard (2d+1)-point Laplacian
+# scaled by 1/h^2 with h = 1/(s+1).  The linear 1D case is c = 0, f = b.
+# --------------------------------------------------------------------------
+
+def laplacian_lambda_max(d: int, s: int) -> float:
+    """Largest eigenvalue of the Dirichlet (2d+1)-point Laplacian, closed form.
+
+    Each 1D factor tridiag(-1, 2, -1)/h^2 has eigenvalues
+    (4/h^2) sin^2(j pi / (2(s+1))), j = 1..s; the largest is j = s, i.e.
+    (4/h^2) cos^2(pi / (2(s+1))).  The d-dimensional operator is a Kronecker
+    sum, so its largest eigenvalue is d times that.
+    """
+    h = 1.0 / (s + 1)
+    return d * (4.0 / (h * h)) * math.cos(math.pi / (2.0 * (s + 1))) ** 2
+
+
+def laplacian_lambda_min(d: int, s: int) -> float:
+    h = 1.0 / (s + 1)
+    return d * (4.0 / (h * h)) * math.sin(math.pi / (2.0 * (s + 1))) ** 2
+
+
+@dataclass
+class StencilProblem:
+    """One instance of G(u) = u - omega (A u + c u^3 - f)."""
+
+    d: int            # grid dimension (1, 2 or 3)
+    s: int            # points per side; n = s**d
+    c: float          # coefficient of the cubic term (0 for the linear case)
+    f: np.ndarray     # right-hand side, length n
+    omega: float = 0.0
+    h: float = 0.0
+
+    def __post_init__(self):
+        self.h = 1.0 / (self.s + 1)
+        if self.omega == 0.0:
+            self.omega = 0.9 / laplacian_lambda_max(self.d, self.s)
+
+    @property
+    def n(self) -> int:
+        return self.s ** self.d
+
+
+# Seeds of the named workloads.
+SEED_POISSON1D_B = 1
+SEED_POISSON3D_F = 2
+SEED_QR_Q = 3
+SEED_QR_V = 4
+SEED_TRAIN_BASE = 1_000_000
+
+
+def poisson1d(n: int = 4096, seed: int = SEED_POISSON1D_B) -> StencilProblem:
+    """Linear 1D Poisson fixed point G(x) = x - omega (A x - b), b ~ U[-1, 1]."""
+    b = 2.0 * uniform(seed, 0, n) - 1.0
+    return StencilProblem(d=1, s=n, c=0.0, f=b)
+
+
+def nonlinear3d(s: int = 256, seed: int = SEED_POISSON3D_F) -> StencilProblem:
+    """3D nonlinear fixed point G(u) = u - omega (A u + u^3 - f), f ~ U[0, 1]."""
+    f = uniform(seed, 0, s ** 3)
+    return StencilProblem(d=3, s=s, c=1.0, f=f)
+
+
+@dataclass
+class BatchInstance:
+    seed: int
+    s: int
+    m: int
+    c: float
+
+    @property
+    def n(self) -> int:
+        return self.s * self.s
+
+
+def batch_instance(seed: int, s_lo: int = 32, s_hi: int = 512, m_lo: int = 3,
+                   m_hi: int = 20) -> BatchInstance:
+    """Parameters of one 2D instance: s log-uniform on [s_lo, s_hi], m uniform
+    on {m_lo..m_hi}, c ~ U[0, 1] (stream 0 of the instance seed)."""
+    u = uniform(seed, 0, 3)
+    s = int(round(s_lo * (s_hi / s_lo) ** u[0]))
+    m = m_lo + int(math.floor((m_hi - m_lo + 1) * u[1]))
+    return BatchInstance(seed=seed, s=s, m=min(m, m_hi), c=float(u[2]))
+
+
+def batch_problem(inst: BatchInstance) -> StencilProblem:
+    """The 2D problem of a batch instance; f ~ U[0, 1] from stream 1."""
+    return StencilProblem(d=2, s=inst.s, c=inst.c, f=uniform(inst.seed, 1, inst.n))
+
+
+def batch_table(count: int = 4096, first_seed: int = 0, **kw) -> list[BatchInstance]:
+    return [batch_instance(first_seed + j, **kw) for j in range(count)]

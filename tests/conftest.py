@@ -1,0 +1,27 @@
+"""Test configuration.
+
+Markers: ``gpu`` tests need an MI355X (gfx950) and the built HIP library;
+everything else runs on the CPU.  The CPU oracle is built once per session if
+its shared object is missing.
+"""
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs a gfx950 GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _oracle_built():
+    import oracle
+    if not os.path.exists(oracle.LIB_PATH):
+        oracle.build()
+    yield
