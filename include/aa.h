@@ -1,0 +1,203 @@
+/*
+ * aa.h -- C ABI of the MI355X (gfx950) Anderson-acceleration library.
+ *
+ * Anderson acceleration (AA) of a fixed-point map G with a window of m past
+ * differences, following Lockhart, Gardner, Woodward, Thomas and Olson,
+ * "Performance of Low Synchronization Orthogonalization Methods in Anderson
+ * Accelerated Fixed Point Solvers" (arXiv 2110.09667):
+ *   Alg. 1  -- the AA iteration,
+ *   Alg. 2  -- the least-squares solve through a windowed QR of F_i
+ *              (QRDelete by Givens rotations when the window is full, then
+ *              QRAdd, then R gamma = Q^T f_i),
+ *   Algs. 3-6 -- QRAdd by MGS, ICWY-MGS, CGS-2 and DCGS-2.
+ * Everything is FP64.  Every step runs in the library's HIP kernels.
+ *
+ * Conventions shared by all entry points
+ * --------------------------------------
+ * - Pointers named d_* are device pointers (HBM of the current HIP device),
+ *   h_* are host pointers.  Vectors of length n are contiguous FP64, 8-byte
+ *   aligned; 16-byte alignment is not required.
+ * - Ownership: the library never allocates device memory.  The caller passes
+ *   a workspace (d_workspace, size from aa_workspace_size, 256-byte aligned)
+ *   that holds Q, the history of G differences, R, T and all scratch; the
+ *   caller keeps it alive until aa_destroy.  The context itself is a small
+ *   host allocation freed by aa_destroy.
+ * - Streams: all device work of a context is enqueued on the stream given to
+ *   aa_init (or aa_set_stream); calls return without waiting unless stated.
+ *   One context must not be used from two host threads at once.
+ * - Errors: every entry point returns an aa_status.  Argument and state errors
+ *   are detected on the host before anything is enqueued and leave the context
+ *   unchanged.  Device-side breakdown (a zero, negative or non-finite R_kk) is
+ *   latched in the workspace and reported by the next aa_get_info.  The
+ *   library never aborts and never prints.
+ */
+#ifndef AA_H
+#define AA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct aa_ctx aa_ctx;
+
+/* QRAdd variants (Sec. 3): Alg. 3, Alg. 5, Alg. 6, Alg. 4. */
+typedef enum { AA_MGS = 0, AA_CGS2 = 1, AA_DCGS2 = 2, AA_ICWY = 3 } aa_variant;
+
+typedef enum {
+  AA_OK = 0,
+  AA_EINVAL = -1,      /* bad argument (size, pointer, alignment, enum)     */
+  AA_EHIP = -2,        /* a HIP runtime call failed                          */
+  AA_EBREAKDOWN = -3,  /* R_kk <= 0 or non-finite: F_i lost full column rank */
+  AA_ESTATE = -4,      /* QRAdd on a full window, QRDelete on an empty one   */
+  AA_ENOSPACE = -5     /* workspace smaller than aa_workspace_size           */
+} aa_status;
+
+/* Flags of aa_init. */
+enum {
+  /* Alg. 6 read literally: R_{0:k-2,k-1} += s.  Default adds R_{k-1,k-1} s,
+   * which keeps Q R = F_i (the factorization Alg. 2 relies on). */
+  AA_DCGS2_LITERAL = 1u << 1,
+  /* Alg. 6: reorthogonalize the previous column when m_i >= 3 instead of the
+   * printed m_i > 3. */
+  AA_DCGS2_GUARD_GE3 = 1u << 4,
+  /* Workspace for the QR update only (aa_qr_add / aa_qr_delete /
+   * aa_qr_solve); aa_step is then unavailable.  Saves (m + 3) n doubles. */
+  AA_QR_ONLY = 1u << 8
+};
+
+/* Largest window (columns of Q).  65 lets a full 64-column basis receive one
+ * more column in the QRAdd microbenchmark. */
+#define AA_MAX_COLS 65
+
+typedef struct {
+  int64_t iter;      /* index i of the next aa_step call                    */
+  int m_i;           /* columns used by the last step (min(m, i))           */
+  int k;             /* columns currently in Q                              */
+  double res_norm;   /* ||f_i||_2 of the last step, f_i = G(x_i) - x_i      */
+  double res0_norm;  /* ||f_0||_2                                           */
+  double step_norm;  /* ||x_{i+1} - x_i||_2 of the last step                */
+  int status;        /* AA_OK or a latched device-side error                */
+} aa_info;
+
+/* Bytes of device workspace for a window of m columns over vectors of
+ * length n (1 <= m <= AA_MAX_COLS, n >= 1). */
+aa_status aa_workspace_size(int64_t n, int m, int variant, unsigned flags,
+                            size_t *bytes);
+
+/* Create a context on the current HIP device.  d_workspace must be 256-byte
+ * aligned and at least aa_workspace_size bytes; it is initialized on
+ * `stream` (a hipStream_t, or NULL for the default stream). */
+aa_status aa_init(aa_ctx **ctx, int64_t n, int m, int variant, unsigned flags,
+                  void *d_workspace, size_t bytes, void *stream);
+
+aa_status aa_set_stream(aa_ctx *ctx, void *stream);
+
+/* One AA iteration (Alg. 1), asynchronous on the context's stream.
+ * Call i = 0 (the first call): d_g = G(x_0); returns x_1 = G(x_0).
+ * Call i >= 1: d_x = x_i, d_g = G(x_i); forms f_i, Delta f_{i-1} and
+ * Delta g_{i-1}, updates the QR of F_i (QRDelete when i > m, then QRAdd),
+ * solves R gamma = Q^T f_i and writes x_{i+1} = G(x_i) - sum gamma_j
+ * Delta g_{i-m_i+j} to d_x_next.  d_x_next may alias d_x but not d_g. */
+aa_status aa_step(aa_ctx *ctx, const double *d_x, const double *d_g,
+                  double *d_x_next);
+
+/* Waits for the context's stream and reports the state of the last step. */
+aa_status aa_get_info(aa_ctx *ctx, aa_info *h_info);
+
+/* QRAdd (Alg. 2 with Alg. 3, 4, 5 or 6): append d_v (length n, not modified)
+ * as column k; k -> k + 1.  AA_ESTATE if k == m. */
+aa_status aa_qr_add(aa_ctx *ctx, const double *d_v);
+
+/* QRDelete (Alg. 2): drop column 0 by Givens rotations; k -> k - 1.
+ * ICWY also refreshes T with one reduction.  AA_ESTATE if k == 0. */
+aa_status aa_qr_delete(aa_ctx *ctx);
+
+/* Solve R gamma = Q^T d_f (Alg. 2, last line); d_gamma receives k doubles
+ * (device).  AA_ESTATE if k == 0. */
+aa_status aa_qr_solve(aa_ctx *ctx, const double *d_f, double *d_gamma);
+
+/* Copy R and T (k x k, column-major, leading dimension k) to host buffers
+ * (either may be NULL) and report k.  Waits for the stream. */
+aa_status aa_get_qr(aa_ctx *ctx, double *h_R, double *h_T, int *k);
+
+/* Device pointer to Q (column j at *d_Q + j * *ldq) and its leading
+ * dimension; Q lives in the caller's workspace. */
+aa_status aa_qr_basis(aa_ctx *ctx, double **d_Q, int64_t *ldq);
+
+/* Load an existing factorization (k columns of Q with leading dimension ldq,
+ * k x k R, optional k x k T) -- used to start the QRAdd microbenchmark from a
+ * given orthonormal basis.  Waits for the stream. */
+aa_status aa_qr_load(aa_ctx *ctx, int k, const double *d_Q, int64_t ldq,
+                     const double *h_R, const double *h_T);
+
+/* Forget the history (k = 0, iteration index 0); keeps the workspace. */
+aa_status aa_reset(aa_ctx *ctx);
+
+aa_status aa_destroy(aa_ctx *ctx);
+
+/* Number of reduction finalizations ("Syncs", Sec. 3) enqueued so far by
+ * QRAdd, QRDelete and the right-hand side Q^T f, for comparison with the
+ * paper's counts (Sec. 4.1).  Host-side counter, no wait. */
+aa_status aa_sync_counts(aa_ctx *ctx, int64_t *add, int64_t *del, int64_t *rhs);
+
+/* ---------------- measurement and tuning ---------------------------------- */
+
+/* Kernel kinds, for per-kernel timing. */
+typedef enum {
+  AA_K_DOTS = 0,    /* block dot products Q^T [x, y] (+ x^T x)            */
+  AA_K_UPDATE = 1,  /* v - Q c with fused dot / norm (+ DCGS-2 reorth)    */
+  AA_K_CGS2B = 2,   /* CGS-2 second pass                                  */
+  AA_K_GIVENS = 3,  /* Givens rotations from R (one wavefront)            */
+  AA_K_ROTATE = 4,  /* rotation sweep over Q (+ ICWY Gram)                */
+  AA_K_SCALE = 5,   /* q_k = w / R_kk                                     */
+  AA_K_HISTORY = 6, /* f_i, Delta f, Delta g                              */
+  AA_K_XUPDATE = 7, /* x_{i+1} = G(x_i) - sum gamma_j Delta g_j           */
+  AA_K_COUNT = 8
+} aa_kernel_kind;
+
+/* Enable (1) or disable (0) per-launch timing: every kernel the context
+ * enqueues is bracketed by two hipEvents on the context's stream (events are
+ * created on the first enable; no device memory is allocated).  Disabling or
+ * aa_profile_reset discards what was recorded. */
+aa_status aa_profile_enable(aa_ctx *ctx, int enable);
+
+/* Totals for one kernel kind since the last reset: elapsed milliseconds
+ * (sum of the event pairs), number of launches, and algorithmic HBM bytes
+ * (each vector a launch must read or write counted once, 8 n bytes per
+ * vector).  Waits for the context's stream. */
+aa_status aa_profile_read(aa_ctx *ctx, int kind, double *ms, int64_t *launches,
+                          double *bytes);
+aa_status aa_profile_reset(aa_ctx *ctx);
+
+/* Upper bounds on the workgroups of the streaming passes and of the ICWY
+ * Gram pass (defaults 1024 and 256; each in [1, 4096]). */
+aa_status aa_set_grid(aa_ctx *ctx, int stream_max, int gram_max);
+
+/* ---------------- model fixed-point maps and seeded inputs --------------- */
+
+/* d_out = d_u - omega (A d_u + c d_u^3 - d_f), A the (2 dim + 1)-point
+ * Dirichlet Laplacian on an s^dim grid (x fastest) scaled by 1/h^2.
+ * dim in {1, 2, 3}; d_out must not alias d_u. */
+aa_status aa_problem_apply(int dim, int64_t s, double h, double omega, double c,
+                           const double *d_f, const double *d_u, double *d_out,
+                           void *stream);
+
+/* Seeded inputs: element i of stream (seed, stream) is SplitMix64's output
+ * function of a per-stream counter origin plus i; uniforms in [0, 1) scaled
+ * to [lo, hi); normals by the Box-Muller cosine branch. */
+aa_status aa_fill_uniform(double *d_out, int64_t n, uint64_t seed,
+                          uint64_t stream_id, uint64_t offset, double lo,
+                          double hi, void *stream);
+aa_status aa_fill_normal(double *d_out, int64_t n, uint64_t seed,
+                         uint64_t stream_id, uint64_t offset, void *stream);
+
+/* Library version string. */
+const char *aa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AA_H */

@@ -1,0 +1,296 @@
+"""ctypes binding of ``libaa.so`` (``include/aa.h``): argument marshalling only.
+
+Every function named ``aa_*`` here calls the C entry point of the same name
+with raw device pointers (``tensor.data_ptr()``) and the HIP stream of the
+current torch stream.  Errors come back as ``AAError`` carrying the status.
+Torch is used for device memory and streams only.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaa.so")
+
+MGS, CGS2, DCGS2, ICWY = 0, 1, 2, 3
+VARIANTS = {"mgs": MGS, "cgs2": CGS2, "dcgs2": DCGS2, "icwy": ICWY}
+DCGS2_LITERAL = 1 << 1
+DCGS2_GUARD_GE3 = 1 << 4
+QR_ONLY = 1 << 8
+MAX_COLS = 65
+
+STATUS = {0: "AA_OK", -1: "AA_EINVAL", -2: "AA_EHIP", -3: "AA_EBREAKDOWN",
+          -4: "AA_ESTATE", -5: "AA_ENOSPACE"}
+
+SYMBOLS = [
+    "aa_workspace_size", "aa_init", "aa_set_stream", "aa_step", "aa_get_info",
+    "aa_qr_add", "aa_qr_delete", "aa_qr_solve", "aa_get_qr", "aa_qr_basis",
+    "aa_qr_load", "aa_reset", "aa_destroy", "aa_sync_counts", "aa_problem_apply",
+    "aa_fill_uniform", "aa_fill_normal", "aa_version", "aa_profile_enable",
+    "aa_profile_read", "aa_profile_reset", "aa_set_grid",
+]
+
+KERNEL_KINDS = ["dots", "update", "cgs2b", "givens", "rotate", "scale", "history", "xupdate"]
+
+
+class AAError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}")
+        self.status = status
+
+
+class Info(C.Structure):
+    _fields_ = [("iter", C.c_int64), ("m_i", C.c_int), ("k", C.c_int),
+                ("res_norm", C.c_double), ("res0_norm", C.c_double),
+                ("step_norm", C.c_double), ("status", C.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Load ``libaa.so``; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    P, I64, I, U, D, U64 = C.c_void_p, C.c_int64, C.c_int, C.c_uint, C.c_double, C.c_uint64
+    sig = {
+        "aa_workspace_size": [I64, I, I, U, C.POINTER(C.c_size_t)],
+        "aa_init": [C.POINTER(P), I64, I, I, U, P, C.c_size_t, P],
+        "aa_set_stream": [P, P],
+        "aa_step": [P, P, P, P],
+        "aa_get_info": [P, C.POINTER(Info)],
+        "aa_qr_add": [P, P],
+        "aa_qr_delete": [P],
+        "aa_qr_solve": [P, P, P],
+        "aa_get_qr": [P, P, P, C.POINTER(C.c_int)],
+        "aa_qr_basis": [P, C.POINTER(P), C.POINTER(I64)],
+        "aa_qr_load": [P, I, P, I64, P, P],
+        "aa_reset": [P],
+        "aa_destroy": [P],
+        "aa_sync_counts": [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)],
+        "aa_problem_apply": [I, I64, D, D, D, P, P, P, P],
+        "aa_fill_uniform": [P, I64, U64, U64, U64, D, D, P],
+        "aa_fill_normal": [P, I64, U64, U64, U64, P],
+        "aa_profile_enable": [P, I],
+        "aa_profile_read": [P, I, C.POINTER(D), C.POINTER(I64), C.POINTER(D)],
+        "aa_profile_reset": [P],
+        "aa_set_grid": [P, I, I],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    L.aa_version.argtypes = []
+    L.aa_version.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise AAError(st, where)
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+# ---- thin wrappers with the C names -----------------------------------------
+
+def aa_workspace_size(n: int, m: int, variant: int, flags: int = 0) -> int:
+    b = C.c_size_t(0)
+    _check(lib().aa_workspace_size(n, m, variant, flags, C.byref(b)), "aa_workspace_size")
+    return b.value
+
+
+def aa_init(n, m, variant, flags, workspace, stream=None):
+    ctx = C.c_void_p()
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(lib().aa_init(C.byref(ctx), n, m, variant, flags, workspace.data_ptr(), nbytes,
+                         _stream(stream)), "aa_init")
+    return ctx
+
+
+def aa_step(ctx, x, g, x_next):
+    _check(lib().aa_step(ctx, _ptr(x), _ptr(g), _ptr(x_next)), "aa_step")
+
+
+def aa_get_info(ctx) -> Info:
+    info = Info()
+    _check(lib().aa_get_info(ctx, C.byref(info)), "aa_get_info")
+    return info
+
+
+def aa_qr_add(ctx, v):
+    _check(lib().aa_qr_add(ctx, _ptr(v)), "aa_qr_add")
+
+
+def aa_qr_delete(ctx):
+    _check(lib().aa_qr_delete(ctx), "aa_qr_delete")
+
+
+def aa_qr_solve(ctx, f, gamma):
+    _check(lib().aa_qr_solve(ctx, _ptr(f), _ptr(gamma)), "aa_qr_solve")
+
+
+def aa_get_qr(ctx, cap: int):
+    import numpy as np
+    R = np.zeros(cap * cap)
+    T = np.zeros(cap * cap)
+    k = C.c_int(0)
+    _check(lib().aa_get_qr(ctx, R.ctypes.data, T.ctypes.data, C.byref(k)), "aa_get_qr")
+    kk = k.value
+    return (R[: kk * kk].reshape(kk, kk, order="F").copy(),
+            T[: kk * kk].reshape(kk, kk, order="F").copy(), kk)
+
+
+def aa_qr_basis(ctx):
+    p = C.c_void_p()
+    ld = C.c_int64(0)
+    _check(lib().aa_qr_basis(ctx, C.byref(p), C.byref(ld)), "aa_qr_basis")
+    return p.value, ld.value
+
+
+def aa_qr_load(ctx, k, Q_ptr, ldq, R, T=None):
+    import numpy as np
+    Rf = np.asfortranarray(R, dtype=np.float64)
+    Tf = None if T is None else np.asfortranarray(T, dtype=np.float64)
+    _check(lib().aa_qr_load(ctx, k, Q_ptr, ldq, Rf.ctypes.data,
+                            None if Tf is None else Tf.ctypes.data), "aa_qr_load")
+
+
+def aa_reset(ctx):
+    _check(lib().aa_reset(ctx), "aa_reset")
+
+
+def aa_destroy(ctx):
+    _check(lib().aa_destroy(ctx), "aa_destroy")
+
+
+def aa_sync_counts(ctx):
+    a, d, r = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().aa_sync_counts(ctx, C.byref(a), C.byref(d), C.byref(r)), "aa_sync_counts")
+    return a.value, d.value, r.value
+
+
+def aa_problem_apply(dim, s, h, omega, c, f, u, out, stream=None):
+    _check(lib().aa_problem_apply(dim, s, h, omega, c, _ptr(f), _ptr(u), _ptr(out),
+                                  _stream(stream)), "aa_problem_apply")
+
+
+def aa_fill_uniform(out, seed, stream_id, offset=0, lo=0.0, hi=1.0, stream=None):
+    _check(lib().aa_fill_uniform(_ptr(out), out.numel(), seed, stream_id, offset, lo, hi,
+                                 _stream(stream)), "aa_fill_uniform")
+
+
+def aa_fill_normal(out, seed, stream_id, offset=0, stream=None):
+    _check(lib().aa_fill_normal(_ptr(out), out.numel(), seed, stream_id, offset,
+                                _stream(stream)), "aa_fill_normal")
+
+
+def aa_profile_enable(ctx, enable=True):
+    _check(lib().aa_profile_enable(ctx, 1 if enable else 0), "aa_profile_enable")
+
+
+def aa_profile_read(ctx, kind: int):
+    ms, n, b = C.c_double(), C.c_int64(), C.c_double()
+    _check(lib().aa_profile_read(ctx, kind, C.byref(ms), C.byref(n), C.byref(b)),
+           "aa_profile_read")
+    return ms.value, n.value, b.value
+
+
+def aa_profile_reset(ctx):
+    _check(lib().aa_profile_reset(ctx), "aa_profile_reset")
+
+
+def aa_set_grid(ctx, stream_max: int, gram_max: int):
+    _check(lib().aa_set_grid(ctx, stream_max, gram_max), "aa_set_grid")
+
+
+def aa_version() -> str:
+    return lib().aa_version().decode()
+
+
+# ---- convenience context ------------------------------------------------------
+
+class AAContext:
+    """Owns a torch workspace and a library context for vectors of length n."""
+
+    def __init__(self, n: int, m: int, variant="mgs", flags: int = 0, device="cuda",
+                 stream=None):
+        import torch
+        self.n, self.m = int(n), int(m)
+        self.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        self.flags = int(flags)
+        nbytes = aa_workspace_size(self.n, self.m, self.variant, self.flags)
+        # 256-byte aligned: torch's caching allocator aligns blocks to >= 512 B
+        self.workspace = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=device)
+        assert self.workspace.data_ptr() % 256 == 0
+        self.ctx = aa_init(self.n, self.m, self.variant, self.flags, self.workspace, stream)
+
+    def step(self, x, g, x_next):
+        aa_step(self.ctx, x, g, x_next)
+
+    def info(self) -> Info:
+        return aa_get_info(self.ctx)
+
+    def qr_add(self, v):
+        aa_qr_add(self.ctx, v)
+
+    def qr_delete(self):
+        aa_qr_delete(self.ctx)
+
+    def qr_solve(self, f, gamma):
+        aa_qr_solve(self.ctx, f, gamma)
+
+    def get_qr(self):
+        return aa_get_qr(self.ctx, self.m)
+
+    def basis(self, k: int | None = None):
+        """Torch view of Q's first k columns as an (n, k) column-major tensor."""
+        import torch
+        ptr, ld = aa_qr_basis(self.ctx)
+        if k is None:
+            k = aa_get_qr(self.ctx, self.m)[2]
+        ws = self.workspace
+        off = (ptr - ws.data_ptr()) // 8
+        return ws.as_strided((self.n, k), (1, ld), off)
+
+    def profile(self, enable=True):
+        aa_profile_enable(self.ctx, enable)
+
+    def profile_read(self):
+        """{kind: (ms, launches, algorithmic bytes)} since the last reset."""
+        return {name: aa_profile_read(self.ctx, i) for i, name in enumerate(KERNEL_KINDS)}
+
+    def set_grid(self, stream_max: int, gram_max: int):
+        aa_set_grid(self.ctx, stream_max, gram_max)
+
+    def sync_counts(self):
+        return aa_sync_counts(self.ctx)
+
+    def reset(self):
+        aa_reset(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            aa_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

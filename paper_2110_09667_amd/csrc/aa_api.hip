@@ -1,0 +1,575 @@
+// aa_api.hip -- host side of the C ABI declared in include/aa.h.
+//
+// The context tracks the iteration index and the column count k on the host
+// (both evolve deterministically), carves the caller's workspace into Q, the
+// history of G differences, the work vectors and the small dense block, and
+// enqueues the kernel sequence of each step on the context's stream.
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "aa_internal.h"
+
+using namespace aa;
+
+struct aa_ctx {
+  int64_t n = 0, ldq = 0;
+  int m = 0, cap = 0, variant = 0;
+  unsigned flags = 0;
+  hipStream_t stream = nullptr;
+  double* Q = nullptr;      // ldq x cap
+  double* ring = nullptr;   // ldq x m (Delta g history), AA only
+  double* W = nullptr;      // ldq (Delta f / MGS work vector)
+  double* f_prev = nullptr; // ldq, AA only
+  double* g_prev = nullptr; // ldq, AA only
+  Small sm{};
+  int grid_stream_max = 1024;  // workgroups of the streaming passes
+  int grid_gram_max = 256;     // workgroups of the ICWY Gram pass
+  int64_t iter = 0;
+  int k = 0, m_i = 0;
+  int64_t syncs_add = 0, syncs_del = 0, syncs_rhs = 0;
+  // per-launch timing (aa_profile_enable)
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev;   // pairs: 2 p (start), 2 p + 1 (stop)
+  std::vector<int> ev_kind;
+  int ev_used = 0;
+  double prof_ms[AA_K_COUNT] = {};
+  int64_t prof_launches[AA_K_COUNT] = {};
+  double prof_bytes[AA_K_COUNT] = {};
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int64_t leading_dim(int64_t n) {
+  // Pad to 64 doubles (512 B); break power-of-two column strides so the
+  // columns of one row tile do not start on the same HBM channel.
+  int64_t ld = (n + 63) / 64 * 64;
+  if (ld >= 4096 && (ld & (ld - 1)) == 0) ld += 64;
+  else if (ld % 4096 == 0) ld += 64;
+  return ld;
+}
+
+struct Layout {
+  int64_t ldq;
+  size_t off_Q, off_ring, off_W, off_fp, off_gp, off_R, off_T, off_c0, off_c1, off_gam,
+      off_giv, off_scal, off_status, off_ticket, off_part, total;
+};
+
+Layout make_layout(int64_t n, int m, unsigned flags) {
+  Layout L{};
+  const int cap = m;
+  L.ldq = leading_dim(n);
+  const size_t vec = (size_t)L.ldq * sizeof(double);
+  size_t o = 0;
+  L.off_Q = o; o = align_up(o + vec * cap);
+  if (!(flags & AA_QR_ONLY)) {
+    L.off_ring = o; o = align_up(o + vec * m);
+    L.off_fp = o; o = align_up(o + vec);
+    L.off_gp = o; o = align_up(o + vec);
+  }
+  L.off_W = o; o = align_up(o + vec);
+  L.off_R = o; o = align_up(o + sizeof(double) * cap * cap);
+  L.off_T = o; o = align_up(o + sizeof(double) * cap * cap);
+  L.off_c0 = o; o = align_up(o + sizeof(double) * cap);
+  L.off_c1 = o; o = align_up(o + sizeof(double) * cap);
+  L.off_gam = o; o = align_up(o + sizeof(double) * cap);
+  L.off_giv = o; o = align_up(o + sizeof(double) * 2 * cap);
+  L.off_scal = o; o = align_up(o + sizeof(double) * S_COUNT);
+  L.off_status = o; o = align_up(o + sizeof(int));
+  L.off_ticket = o; o = align_up(o + sizeof(unsigned));
+  const size_t part = (size_t)kMaxRed * 1024 > (size_t)kMaxPairs * 256
+                          ? (size_t)kMaxRed * 1024 : (size_t)kMaxPairs * 256;
+  L.off_part = o; o = align_up(o + sizeof(double) * part);
+  L.total = o;
+  return L;
+}
+
+bool valid_variant(int v) { return v >= AA_MGS && v <= AA_ICWY; }
+
+aa_status hip_ok(hipError_t e) { return e == hipSuccess ? AA_OK : AA_EHIP; }
+
+int grid_for(const aa_ctx* c, int64_t rows_per_wg, int gmax) {
+  int64_t g = (c->n + rows_per_wg - 1) / rows_per_wg;
+  if (g > gmax) g = gmax;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+int grid_stream(const aa_ctx* c) { return grid_for(c, kTile, c->grid_stream_max); }
+int grid_rows(const aa_ctx* c, int gmax) { return grid_for(c, kWG, gmax); }
+
+constexpr int kEventPairs = 4096;
+
+hipError_t prof_drain(aa_ctx* c) {
+  if (c->ev_used == 0) return hipSuccess;
+  hipError_t e = hipEventSynchronize(c->ev[2 * (c->ev_used - 1) + 1]);
+  if (e != hipSuccess) return e;
+  for (int p = 0; p < c->ev_used; ++p) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, c->ev[2 * p], c->ev[2 * p + 1]);
+    if (e != hipSuccess) return e;
+    c->prof_ms[c->ev_kind[p]] += ms;
+  }
+  c->ev_used = 0;
+  return hipSuccess;
+}
+
+// Enqueue one kernel; with profiling on, bracket it with an event pair and
+// account `vecs` algorithmic vector transfers (8 n bytes each) to its kind.
+template <class F>
+hipError_t timed(aa_ctx* c, int kind, double vecs, F&& launch) {
+  if (!c->prof_on) return launch();
+  if (c->ev_used == kEventPairs) {
+    hipError_t e = prof_drain(c);
+    if (e != hipSuccess) return e;
+  }
+  const int p = c->ev_used;
+  hipError_t e = hipEventRecord(c->ev[2 * p], c->stream);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(c->ev[2 * p + 1], c->stream);
+  if (e != hipSuccess) return e;
+  c->ev_kind[p] = kind;
+  c->ev_used = p + 1;
+  c->prof_launches[kind] += 1;
+  c->prof_bytes[kind] += vecs * 8.0 * (double)c->n;
+  return hipSuccess;
+}
+
+Tail tail(int op, int k) {
+  Tail t{};
+  t.op = op;
+  t.k = k;
+  return t;
+}
+
+// QRAdd of d_v as column k (Algs. 3-6); d_v is read-only.
+aa_status qr_add_impl(aa_ctx* c, const double* v) {
+  const int k = c->k;
+  if (k >= c->cap) return AA_ESTATE;
+  const hipStream_t st = c->stream;
+  const int G = grid_stream(c);
+  double* slotk = c->Q + (int64_t)k * c->ldq;
+  double* Rcol = c->sm.R + (size_t)k * c->sm.cap;
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+
+  DotsArgs d{c->Q, c->ldq, c->n, v, 0, nullptr, 0, 0};
+  UpdArgs u{};
+  u.Q = c->Q; u.ldq = c->ldq; u.n = c->n; u.Qw = c->Q; u.dotcol = -1; u.dcgs2_p = -1;
+  Tail tn = tail(TAIL_NORM, k);
+  tn.idx = 0;
+
+  if (k == 0) {
+    // Alg. 2 with i = 1 (and every QRAdd into an empty window): normalize.
+    d.xx = 1;
+    chk(timed(c, AA_K_DOTS, 1, [&] { return launch_dots(d, c->sm, tn, G, st); }));
+    c->syncs_add += 1;
+  } else {
+    switch (c->variant) {
+      case AA_MGS: {
+        Tail t0 = tail(TAIL_MGS_R, k);
+        t0.row = 0;
+        d.nx = 1;
+        chk(timed(c, AA_K_DOTS, 2, [&] { return launch_dots(d, c->sm, t0, G, st); }));
+        const double* cur = v;
+        for (int j = 1; j < k; ++j) {
+          UpdArgs uj = u;
+          uj.v = cur; uj.out = c->W; uj.j0 = j - 1; uj.nc = 1; uj.c1 = Rcol; uj.dotcol = j;
+          Tail tj = tail(TAIL_MGS_R, k);
+          tj.row = j;
+          chk(timed(c, AA_K_UPDATE, 4, [&] { return launch_update(uj, c->sm, tj, G, st); }));
+          cur = c->W;
+        }
+        UpdArgs uk = u;
+        uk.v = cur; uk.out = slotk; uk.j0 = k - 1; uk.nc = 1; uk.c1 = Rcol; uk.nrm = 1;
+        chk(timed(c, AA_K_UPDATE, 3, [&] { return launch_update(uk, c->sm, tn, G, st); }));
+        c->syncs_add += k + 1;
+        break;
+      }
+      case AA_CGS2: {
+        d.nx = k;
+        chk(timed(c, AA_K_DOTS, k + 1,
+                  [&] { return launch_dots(d, c->sm, tail(TAIL_CGS2_S, k), G, st); }));
+        Cgs2bArgs b{c->Q, c->ldq, c->n, v, k, c->sm.coef0};
+        const int Gb = grid_rows(c, c->grid_stream_max);
+        chk(timed(c, AA_K_CGS2B, k + 1,
+                  [&] { return launch_cgs2b(b, c->sm, tail(TAIL_CGS2_Z, k), Gb, st); }));
+        UpdArgs uc = u;
+        uc.v = v; uc.out = slotk; uc.j0 = 0; uc.nc = k; uc.c1 = c->sm.coef0; uc.c2 = c->sm.coef1;
+        uc.nrm = 1;
+        chk(timed(c, AA_K_UPDATE, k + 2, [&] { return launch_update(uc, c->sm, tn, G, st); }));
+        c->syncs_add += 3;
+        break;
+      }
+      case AA_ICWY: {
+        d.nx = k;
+        d.y = c->Q + (int64_t)(k - 1) * c->ldq;
+        d.ny = k - 1;
+        chk(timed(c, AA_K_DOTS, k + 1,
+                  [&] { return launch_dots(d, c->sm, tail(TAIL_ICWY, k), G, st); }));
+        UpdArgs ub = u;
+        ub.v = v; ub.out = slotk; ub.j0 = 0; ub.nc = k; ub.c1 = c->sm.coef0; ub.nrm = 1;
+        chk(timed(c, AA_K_UPDATE, k + 2, [&] { return launch_update(ub, c->sm, tn, G, st); }));
+        c->syncs_add += 2;
+        break;
+      }
+      case AA_DCGS2: {
+        const int m_i = k + 1;
+        const bool reorth = (c->flags & AA_DCGS2_GUARD_GE3) ? (m_i >= 3) : (m_i > 3);
+        d.nx = k;
+        d.y = c->Q + (int64_t)(k - 1) * c->ldq;
+        d.ny = reorth ? k - 1 : 0;
+        Tail ta = tail(TAIL_DCGS2, k);
+        ta.reorth = reorth;
+        ta.literal = (c->flags & AA_DCGS2_LITERAL) ? 1 : 0;
+        chk(timed(c, AA_K_DOTS, k + 1, [&] { return launch_dots(d, c->sm, ta, G, st); }));
+        UpdArgs ub = u;
+        ub.v = v; ub.out = slotk; ub.c1 = Rcol; ub.nrm = 1;
+        if (reorth) {
+          ub.dcgs2_p = k - 1; ub.reorth = 1; ub.s = c->sm.coef1; ub.j0 = 0; ub.nc = k - 1;
+        } else {
+          ub.j0 = 0; ub.nc = k;
+        }
+        chk(timed(c, AA_K_UPDATE, k + (reorth ? 3 : 2),
+                  [&] { return launch_update(ub, c->sm, tn, G, st); }));
+        c->syncs_add += 2;
+        break;
+      }
+      default:
+        return AA_EINVAL;
+    }
+  }
+  ScaleArgs sa{k == 0 ? v : slotk, slotk, c->n, c->sm.R, k, c->sm.cap};
+  chk(timed(c, AA_K_SCALE, 2, [&] { return launch_scale(sa, c->sm, st); }));
+  if (e != hipSuccess) return AA_EHIP;
+  c->k = k + 1;
+  return AA_OK;
+}
+
+aa_status qr_delete_impl(aa_ctx* c) {
+  const int k = c->k;
+  if (k <= 0) return AA_ESTATE;
+  if (k == 1) {
+    c->k = 0;
+    return AA_OK;
+  }
+  hipError_t e = timed(c, AA_K_GIVENS, 0, [&] { return launch_givens(c->sm, k, c->stream); });
+  if (e != hipSuccess) return AA_EHIP;
+  const bool gram = c->variant == AA_ICWY;
+  RotArgs r{c->Q, c->ldq, c->n, k, c->sm.givens, gram ? 1 : 0};
+  const int G = grid_rows(c, gram ? c->grid_gram_max : c->grid_stream_max);
+  e = timed(c, AA_K_ROTATE, 2 * k - 1,
+            [&] { return launch_rotate(r, c->sm, tail(TAIL_GRAM, k - 1), G, c->stream); });
+  if (e != hipSuccess) return AA_EHIP;
+  if (gram) c->syncs_del += 1;
+  c->k = k - 1;
+  return AA_OK;
+}
+
+aa_status rhs_impl(aa_ctx* c, const double* f) {
+  DotsArgs d{c->Q, c->ldq, c->n, f, c->k, nullptr, 0, 0};
+  const int G = grid_stream(c);
+  hipError_t e = timed(c, AA_K_DOTS, c->k + 1,
+                       [&] { return launch_dots(d, c->sm, tail(TAIL_RHS, c->k), G, c->stream); });
+  c->syncs_rhs += 1;
+  return hip_ok(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+aa_status aa_workspace_size(int64_t n, int m, int variant, unsigned flags, size_t* bytes) {
+  if (!bytes || n < 1 || m < 1 || m > AA_MAX_COLS || !valid_variant(variant)) return AA_EINVAL;
+  if (variant == AA_ICWY && m > 64) return AA_EINVAL;
+  *bytes = make_layout(n, m, flags).total;
+  return AA_OK;
+}
+
+aa_status aa_init(aa_ctx** ctx, int64_t n, int m, int variant, unsigned flags,
+                  void* d_workspace, size_t bytes, void* stream) {
+  if (!ctx) return AA_EINVAL;
+  *ctx = nullptr;
+  size_t need = 0;
+  aa_status s = aa_workspace_size(n, m, variant, flags, &need);
+  if (s != AA_OK) return s;
+  if (!d_workspace || ((uintptr_t)d_workspace % kAlign) != 0) return AA_EINVAL;
+  if (bytes < need) return AA_ENOSPACE;
+  aa_ctx* c = new (std::nothrow) aa_ctx();
+  if (!c) return AA_EINVAL;
+  const Layout L = make_layout(n, m, flags);
+  char* base = (char*)d_workspace;
+  c->n = n;
+  c->ldq = L.ldq;
+  c->m = m;
+  c->cap = m;
+  c->variant = variant;
+  c->flags = flags;
+  c->stream = (hipStream_t)stream;
+  c->Q = (double*)(base + L.off_Q);
+  if (!(flags & AA_QR_ONLY)) {
+    c->ring = (double*)(base + L.off_ring);
+    c->f_prev = (double*)(base + L.off_fp);
+    c->g_prev = (double*)(base + L.off_gp);
+  }
+  c->W = (double*)(base + L.off_W);
+  c->sm.R = (double*)(base + L.off_R);
+  c->sm.T = (double*)(base + L.off_T);
+  c->sm.coef0 = (double*)(base + L.off_c0);
+  c->sm.coef1 = (double*)(base + L.off_c1);
+  c->sm.gamma = (double*)(base + L.off_gam);
+  c->sm.givens = (double*)(base + L.off_giv);
+  c->sm.scal = (double*)(base + L.off_scal);
+  c->sm.status = (int*)(base + L.off_status);
+  c->sm.ticket = (unsigned*)(base + L.off_ticket);
+  c->sm.partials = (double*)(base + L.off_part);
+  c->sm.cap = m;
+  if (launch_init_small(c->sm, c->stream) != hipSuccess) {
+    delete c;
+    return AA_EHIP;
+  }
+  *ctx = c;
+  return AA_OK;
+}
+
+aa_status aa_set_stream(aa_ctx* c, void* stream) {
+  if (!c) return AA_EINVAL;
+  c->stream = (hipStream_t)stream;
+  return AA_OK;
+}
+
+aa_status aa_step(aa_ctx* c, const double* x, const double* g, double* x_next) {
+  if (!c || !x || !g || !x_next || (c->flags & AA_QR_ONLY)) return AA_EINVAL;
+  if (x_next == g) return AA_EINVAL;
+  const hipStream_t st = c->stream;
+  const int G = grid_stream(c);
+  if (c->iter == 0) {
+    // Alg. 1 before the loop: x_1 = G(x_0), f_0 = G(x_0) - x_0.
+    HistArgs h{x, g, c->W, c->f_prev, c->g_prev, nullptr, x_next, c->n, 1};
+    if (timed(c, AA_K_HISTORY, 5,
+              [&] { return launch_history(h, c->sm, tail(TAIL_FIRST, 0), G, st); }) != hipSuccess)
+      return AA_EHIP;
+    c->iter = 1;
+    c->m_i = 0;
+    return AA_OK;
+  }
+  const int64_t i = c->iter;
+  const int m = c->m;
+  const int m_i = (int)(i < m ? i : m);
+  const int slot = (int)((i - 1) % m);
+  HistArgs h{x, g, c->W, c->f_prev, c->g_prev, c->ring + (int64_t)slot * c->ldq, nullptr,
+             c->n, 0};
+  if (timed(c, AA_K_HISTORY, 8,
+            [&] { return launch_history(h, c->sm, tail(TAIL_RES, 0), G, st); }) != hipSuccess)
+    return AA_EHIP;
+  aa_status s = AA_OK;
+  if (i > m) s = qr_delete_impl(c);        // Alg. 2: QRDelete when the window is full
+  if (s == AA_OK) s = qr_add_impl(c, c->W);  // Alg. 2: QRAdd of Delta f_{i-1}
+  if (s == AA_OK) s = rhs_impl(c, c->f_prev);  // R gamma = Q^T f_i
+  if (s != AA_OK) return s;
+  XupdArgs xa{c->ring, c->ldq, m, (int)((i - m_i) % m), m_i, g, x, x_next, c->n, c->sm.gamma};
+  if (timed(c, AA_K_XUPDATE, m_i + 3,
+            [&] { return launch_xupdate(xa, c->sm, tail(TAIL_STEP, 0), G, st); }) != hipSuccess)
+    return AA_EHIP;
+  c->m_i = m_i;
+  c->iter = i + 1;
+  return AA_OK;
+}
+
+aa_status aa_get_info(aa_ctx* c, aa_info* info) {
+  if (!c || !info) return AA_EINVAL;
+  double sc[S_COUNT];
+  int status = 0;
+  if (hipMemcpyAsync(sc, c->sm.scal, sizeof(sc), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return AA_EHIP;
+  if (hipMemcpyAsync(&status, c->sm.status, sizeof(int), hipMemcpyDeviceToHost, c->stream) !=
+      hipSuccess)
+    return AA_EHIP;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return AA_EHIP;
+  info->iter = c->iter;
+  info->m_i = c->m_i;
+  info->k = c->k;
+  info->res_norm = sqrt(sc[S_RES]);
+  info->res0_norm = sqrt(sc[S_RES0]);
+  info->step_norm = sqrt(sc[S_STEP]);
+  info->status = status;
+  return AA_OK;
+}
+
+aa_status aa_qr_add(aa_ctx* c, const double* v) {
+  if (!c || !v) return AA_EINVAL;
+  return qr_add_impl(c, v);
+}
+
+aa_status aa_qr_delete(aa_ctx* c) {
+  if (!c) return AA_EINVAL;
+  return qr_delete_impl(c);
+}
+
+aa_status aa_qr_solve(aa_ctx* c, const double* f, double* gamma) {
+  if (!c || !f || !gamma) return AA_EINVAL;
+  if (c->k == 0) return AA_ESTATE;
+  aa_status s = rhs_impl(c, f);
+  if (s != AA_OK) return s;
+  return hip_ok(launch_copy(gamma, c->sm.gamma, c->k, c->stream));
+}
+
+aa_status aa_get_qr(aa_ctx* c, double* hR, double* hT, int* k) {
+  if (!c) return AA_EINVAL;
+  const int kk = c->k, cap = c->sm.cap;
+  if (k) *k = kk;
+  if (kk == 0) return hip_ok(hipStreamSynchronize(c->stream));
+  if (hR && hipMemcpy2DAsync(hR, kk * sizeof(double), c->sm.R, cap * sizeof(double),
+                             kk * sizeof(double), kk, hipMemcpyDeviceToHost,
+                             c->stream) != hipSuccess)
+    return AA_EHIP;
+  if (hT && hipMemcpy2DAsync(hT, kk * sizeof(double), c->sm.T, cap * sizeof(double),
+                             kk * sizeof(double), kk, hipMemcpyDeviceToHost,
+                             c->stream) != hipSuccess)
+    return AA_EHIP;
+  return hip_ok(hipStreamSynchronize(c->stream));
+}
+
+aa_status aa_qr_basis(aa_ctx* c, double** dQ, int64_t* ldq) {
+  if (!c || !dQ || !ldq) return AA_EINVAL;
+  *dQ = c->Q;
+  *ldq = c->ldq;
+  return AA_OK;
+}
+
+aa_status aa_qr_load(aa_ctx* c, int k, const double* dQ, int64_t ldq, const double* hR,
+                     const double* hT) {
+  if (!c || k < 0 || k > c->cap || (k > 0 && (!dQ || !hR)) || ldq < c->n) return AA_EINVAL;
+  const int cap = c->sm.cap;
+  if (k > 0) {
+    if (hipMemcpy2DAsync(c->Q, c->ldq * sizeof(double), dQ, ldq * sizeof(double),
+                         c->n * sizeof(double), k, hipMemcpyDeviceToDevice,
+                         c->stream) != hipSuccess)
+      return AA_EHIP;
+    // full cap x cap images so that entries outside the k x k block are zero
+    double* R = (double*)calloc((size_t)cap * cap, sizeof(double));
+    double* T = (double*)calloc((size_t)cap * cap, sizeof(double));
+    if (!R || !T) {
+      free(R);
+      free(T);
+      return AA_EINVAL;
+    }
+    for (int j = 0; j < cap; ++j) T[j + (size_t)j * cap] = 1.0;
+    for (int j = 0; j < k; ++j)
+      for (int i = 0; i < k; ++i) {
+        R[i + (size_t)j * cap] = hR[i + (size_t)j * k];
+        if (hT && i != j) T[i + (size_t)j * cap] = hT[i + (size_t)j * k];
+      }
+    hipError_t e1 = hipMemcpyAsync(c->sm.R, R, sizeof(double) * cap * cap,
+                                   hipMemcpyHostToDevice, c->stream);
+    hipError_t e2 = hipMemcpyAsync(c->sm.T, T, sizeof(double) * cap * cap,
+                                   hipMemcpyHostToDevice, c->stream);
+    hipError_t e3 = hipStreamSynchronize(c->stream);
+    free(R);
+    free(T);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return AA_EHIP;
+  }
+  c->k = k;
+  return AA_OK;
+}
+
+aa_status aa_reset(aa_ctx* c) {
+  if (!c) return AA_EINVAL;
+  c->iter = 0;
+  c->k = 0;
+  c->m_i = 0;
+  return hip_ok(launch_init_small(c->sm, c->stream));
+}
+
+aa_status aa_destroy(aa_ctx* c) {
+  if (!c) return AA_OK;
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+  return AA_OK;
+}
+
+aa_status aa_profile_enable(aa_ctx* c, int enable) {
+  if (!c) return AA_EINVAL;
+  if (enable && c->ev.empty()) {
+    c->ev.resize(2 * kEventPairs);
+    c->ev_kind.resize(kEventPairs);
+    for (auto& e : c->ev)
+      if (hipEventCreate(&e) != hipSuccess) return AA_EHIP;
+  }
+  c->prof_on = enable != 0;
+  return aa_profile_reset(c);
+}
+
+aa_status aa_profile_reset(aa_ctx* c) {
+  if (!c) return AA_EINVAL;
+  if (c->ev_used && hipStreamSynchronize(c->stream) != hipSuccess) return AA_EHIP;
+  c->ev_used = 0;
+  for (int k = 0; k < AA_K_COUNT; ++k) {
+    c->prof_ms[k] = 0.0;
+    c->prof_launches[k] = 0;
+    c->prof_bytes[k] = 0.0;
+  }
+  return AA_OK;
+}
+
+aa_status aa_profile_read(aa_ctx* c, int kind, double* ms, int64_t* launches, double* bytes) {
+  if (!c || kind < 0 || kind >= AA_K_COUNT) return AA_EINVAL;
+  if (prof_drain(c) != hipSuccess) return AA_EHIP;
+  if (ms) *ms = c->prof_ms[kind];
+  if (launches) *launches = c->prof_launches[kind];
+  if (bytes) *bytes = c->prof_bytes[kind];
+  return AA_OK;
+}
+
+aa_status aa_set_grid(aa_ctx* c, int stream_max, int gram_max) {
+  if (!c || stream_max < 1 || stream_max > 4096 || gram_max < 1 || gram_max > 4096)
+    return AA_EINVAL;
+  // the partials buffer holds kMaxRed x 1024 and kMaxPairs x 256 values
+  if ((size_t)stream_max * kMaxRed > (size_t)kMaxRed * 1024 ||
+      (size_t)gram_max * kMaxPairs > (size_t)kMaxPairs * 256)
+    return AA_EINVAL;
+  c->grid_stream_max = stream_max;
+  c->grid_gram_max = gram_max;
+  return AA_OK;
+}
+
+aa_status aa_sync_counts(aa_ctx* c, int64_t* add, int64_t* del, int64_t* rhs) {
+  if (!c) return AA_EINVAL;
+  if (add) *add = c->syncs_add;
+  if (del) *del = c->syncs_del;
+  if (rhs) *rhs = c->syncs_rhs;
+  return AA_OK;
+}
+
+aa_status aa_problem_apply(int dim, int64_t s, double h, double omega, double c,
+                           const double* f, const double* u, double* out, void* stream) {
+  if (dim < 1 || dim > 3 || s < 1 || !f || !u || !out || u == out || !(h > 0.0))
+    return AA_EINVAL;
+  return hip_ok(launch_stencil(dim, s, h, omega, c, f, u, out, (hipStream_t)stream));
+}
+
+aa_status aa_fill_uniform(double* out, int64_t n, uint64_t seed, uint64_t stream_id,
+                          uint64_t offset, double lo, double hi, void* stream) {
+  if (!out || n < 0) return AA_EINVAL;
+  if (n == 0) return AA_OK;
+  return hip_ok(launch_fill_uniform(out, n, seed, stream_id, offset, lo, hi, (hipStream_t)stream));
+}
+
+aa_status aa_fill_normal(double* out, int64_t n, uint64_t seed, uint64_t stream_id,
+                         uint64_t offset, void* stream) {
+  if (!out || n < 0) return AA_EINVAL;
+  if (n == 0) return AA_OK;
+  return hip_ok(launch_fill_normal(out, n, seed, stream_id, offset, (hipStream_t)stream));
+}
+
+const char* aa_version(void) { return "aa-mi355x 0.1 (gfx950, fp64)"; }
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+// aa_internal.h -- definitions shared by the kernel and host translation units
+// of the Anderson-acceleration library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/aa.h"
+
+namespace aa {
+
+constexpr int kWG = 256;             // threads per workgroup (4 wave64s)
+constexpr int kWaves = kWG / 64;
+constexpr int kRPT = 8;              // rows per thread per tile in streaming passes
+constexpr int kTile = kWG * kRPT;    // rows per tile in streaming passes
+constexpr int kMaxCols = AA_MAX_COLS;
+constexpr int kMaxRed = 2 * kMaxCols + 4;  // reductions of one streaming pass
+constexpr int kMaxPairs = (kMaxCols - 1) * (kMaxCols - 2) / 2;  // Gram after delete
+
+// Scalar slots in the small device block.
+enum Scal : int { S_RES = 0, S_RES0 = 1, S_STEP = 2, S_COUNT = 8 };
+
+// What the last-arriving workgroup does with the reduced values.
+enum TailOp : int {
+  TAIL_NONE = 0,
+  TAIL_STORE,     // coef0[t] = red[t], t < count
+  TAIL_MGS_R,     // R[row, k] = red[0]
+  TAIL_NORM,      // R[k, k] = sqrt(red[idx]); breakdown check
+  TAIL_CGS2_S,    // coef0 = s = red[0:k]
+  TAIL_CGS2_Z,    // coef1 = z = red[0:k]; R[0:k-1, k] = s + z
+  TAIL_ICWY,      // T row k-1 from red[k:2k-1]; forward solve; R col, coef0
+  TAIL_DCGS2,     // R col k = red[0:k]; s = red[k:2k-1] -> coef1; R col k-1 fix
+  TAIL_RHS,       // c = red[0:k]; back substitution -> gamma
+  TAIL_RES,       // scal[S_RES] = red[0]
+  TAIL_FIRST,     // scal[S_RES0] = scal[S_RES] = red[0], scal[S_STEP] = red[1]
+  TAIL_STEP,      // scal[S_STEP] = red[0]
+  TAIL_GRAM       // T strict lower from pair sums
+};
+
+// Device-resident small dense state (pointers into the workspace).
+struct Small {
+  double* R;        // cap x cap, column-major
+  double* T;        // cap x cap, column-major, unit lower (ICWY)
+  double* coef0;    // cap
+  double* coef1;    // cap
+  double* gamma;    // cap
+  double* givens;   // 2 * cap: cosines then sines
+  double* scal;     // S_COUNT scalars
+  int* status;      // latched aa_status
+  double* partials; // reduction partials, [nred][grid]
+  unsigned* ticket; // arrival counter of the last-workgroup reduction
+  int cap;
+};
+
+struct Tail {
+  int op;
+  int k;        // columns in Q when the pass runs
+  int row;      // TAIL_MGS_R: R row
+  int count;    // TAIL_STORE: values
+  int idx;      // TAIL_NORM: index of the squared norm in red[]
+  int reorth;   // TAIL_DCGS2
+  int literal;  // TAIL_DCGS2
+};
+
+// ---- streaming passes -------------------------------------------------------
+
+// red[j] = Q_j^T x (j < nx); red[nx + j] = Q_j^T y (j < ny); red[nx+ny] = x^T x
+struct DotsArgs {
+  const double* Q; int64_t ldq; int64_t n;
+  const double* x; int nx;
+  const double* y; int ny;
+  int xx;
+};
+
+// out = v - sum_{j0 <= j < j0+nc} Q_j (c1[j] + c2[j]) evaluated as
+// (v - Q c1) - Q c2; optional fused dot Q_{dotcol}^T out and out^T out.
+// DCGS-2 mode (dcgs2_p >= 0): with p = dcgs2_p, first
+//   q'_p = q_p - sum_{j<p} Q_j s[j]   (written back to column p if reorth),
+// then out = v - sum_{j<p} Q_j c1[j] - q'_p c1[p].
+struct UpdArgs {
+  const double* Q; int64_t ldq; int64_t n;
+  double* Qw;            // writable alias of Q (DCGS-2 writes column p)
+  const double* v;
+  double* out;           // may be null (no write) or alias v
+  int j0, nc;
+  const double* c1;      // device coefficients, indexed by absolute column
+  const double* c2;      // may be null
+  int dotcol;            // -1: none
+  int nrm;               // 1: add out^T out
+  int dcgs2_p;           // -1: off
+  int reorth;
+  const double* s;       // DCGS-2 reorthogonalization coefficients
+};
+
+struct Cgs2bArgs {       // y = v - Q s (registers), red[j] = Q_j^T y
+  const double* Q; int64_t ldq; int64_t n;
+  const double* v; int k;
+  const double* s;
+};
+
+struct RotArgs {         // Givens sweep over k columns (+ ICWY Gram of k-1)
+  double* Q; int64_t ldq; int64_t n; int k;
+  const double* givens;
+  int gram;
+};
+
+struct ScaleArgs { const double* in; double* out; int64_t n; const double* R; int kk; int cap; };
+
+struct HistArgs {        // i >= 1: history formation; i == 0: first step
+  const double* x; const double* g;
+  double* W; double* f_prev; double* g_prev; double* dg;  // dg: ring slot
+  double* x_next;        // first step only
+  int64_t n; int first;
+};
+
+struct XupdArgs {
+  const double* ring; int64_t ldq; int m; int slot0; int mi;
+  const double* g; const double* x; double* x_next; int64_t n;
+  const double* gamma;
+};
+
+// launchers (aa_kernels.hip)
+hipError_t launch_dots(const DotsArgs&, const Small&, const Tail&, int grid, hipStream_t);
+hipError_t launch_update(const UpdArgs&, const Small&, const Tail&, int grid, hipStream_t);
+hipError_t launch_cgs2b(const Cgs2bArgs&, const Small&, const Tail&, int grid, hipStream_t);
+hipError_t launch_givens(const Small&, int k, hipStream_t);
+hipError_t launch_rotate(const RotArgs&, const Small&, const Tail&, int grid, hipStream_t);
+hipError_t launch_scale(const ScaleArgs&, const Small&, hipStream_t);
+hipError_t launch_history(const HistArgs&, const Small&, const Tail&, int grid, hipStream_t);
+hipError_t launch_xupdate(const XupdArgs&, const Small&, const Tail&, int grid, hipStream_t);
+hipError_t launch_init_small(const Small&, hipStream_t);
+hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t);
+
+// problems and generators (aa_problems.hip)
+hipError_t launch_stencil(int dim, int64_t s, double h, double omega, double c,
+                          const double* f, const double* u, double* out, hipStream_t);
+hipError_t launch_fill_uniform(double* out, int64_t n, uint64_t seed, uint64_t stream_id,
+                               uint64_t offset, double lo, double hi, hipStream_t);
+hipError_t launch_fill_normal(double* out, int64_t n, uint64_t seed, uint64_t stream_id,
+                              uint64_t offset, hipStream_t);
+
+}  // namespace aa

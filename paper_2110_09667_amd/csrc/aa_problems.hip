@@ -1,0 +1,111 @@
+// aa_problems.hip -- model fixed-point maps and seeded input generators.
+//
+// G(u) = u - omega (A u + c u^3 - f), A the (2 dim + 1)-point Dirichlet
+// Laplacian on an s^dim grid (x fastest) scaled by 1/h^2: the 1D Poisson,
+// 3D nonlinear and 2D batched workloads all use it (dim = 1, 3, 2).
+#include <math.h>
+
+#include "aa_internal.h"
+
+namespace aa {
+
+__global__ __launch_bounds__(256) void k_stencil(int dim, int64_t s, double ih2, double omega,
+                                                 double c, const double* __restrict__ f,
+                                                 const double* __restrict__ u,
+                                                 double* __restrict__ out, int64_t n) {
+  const int64_t s2 = s * s;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ix = p % s;
+    const double up = u[p];
+    double nb = 0.0;
+    if (ix > 0) nb += u[p - 1];
+    if (ix < s - 1) nb += u[p + 1];
+    if (dim >= 2) {
+      const int64_t iy = (p / s) % s;
+      if (iy > 0) nb += u[p - s];
+      if (iy < s - 1) nb += u[p + s];
+    }
+    if (dim >= 3) {
+      const int64_t iz = p / s2;
+      if (iz > 0) nb += u[p - s2];
+      if (iz < s - 1) nb += u[p + s2];
+    }
+    const double au = (2.0 * dim * up - nb) * ih2;
+    out[p] = up - omega * (au + c * up * up * up - f[p]);
+  }
+}
+
+hipError_t launch_stencil(int dim, int64_t s, double h, double omega, double c,
+                          const double* f, const double* u, double* out, hipStream_t st) {
+  int64_t n = s;
+  if (dim >= 2) n *= s;
+  if (dim >= 3) n *= s;
+  int64_t blocks = (n + 255) / 256;
+  int grid = (int)(blocks < 65536 ? blocks : 65536);
+  hipLaunchKernelGGL(k_stencil, dim3(grid), dim3(256), 0, st, dim, s, 1.0 / (h * h), omega, c,
+                     f, u, out, n);
+  return hipGetLastError();
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): output function of z + golden gamma.
+__device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+static uint64_t sm64_mix_host(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// counter origin of stream (seed, stream_id)
+static uint64_t stream_base(uint64_t seed, uint64_t stream_id) {
+  return sm64_mix_host(sm64_mix_host(seed) + stream_id);
+}
+
+__device__ __forceinline__ double u01(uint64_t z) {
+  return (double)(sm64_mix(z) >> 11) * 0x1.0p-53;
+}
+
+__global__ void k_fill_uniform(double* out, int64_t n, uint64_t base, double lo, double hi) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = lo + (hi - lo) * u01(base + (uint64_t)i);
+}
+
+__global__ void k_fill_normal(double* out, int64_t n, uint64_t base, uint64_t offset) {
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t e = 2 * (offset + (uint64_t)i);
+    const double u1 = u01(base + e), u2 = u01(base + e + 1);
+    out[i] = sqrt(-2.0 * log1p(-u1)) * cos(two_pi * u2);
+  }
+}
+
+hipError_t launch_fill_uniform(double* out, int64_t n, uint64_t seed, uint64_t stream_id,
+                               uint64_t offset, double lo, double hi, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  int grid = (int)(blocks < 65536 ? blocks : 65536);
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_fill_uniform, dim3(grid), dim3(256), 0, st, out, n,
+                     stream_base(seed, stream_id) + offset, lo, hi);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_normal(double* out, int64_t n, uint64_t seed, uint64_t stream_id,
+                              uint64_t offset, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  int grid = (int)(blocks < 65536 ? blocks : 65536);
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_fill_normal, dim3(grid), dim3(256), 0, st, out, n,
+                     stream_base(seed, stream_id), offset);
+  return hipGetLastError();
+}
+
+}  // namespace aa

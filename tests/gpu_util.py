@@ -1,0 +1,47 @@
+"""Helpers of the GPU tests: device checks and the HIP-path drivers.
+
+The HIP side is driven only through the C ABI (``paper_2110_09667_amd.aa``);
+the expected values come only from ``oracle`` on the same seeded inputs.
+"""
+import numpy as np
+import pytest
+
+
+def device():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2110_09667_amd import aa
+    aa.lib()  # raises if the HIP library is missing: no silent fallback
+    return torch.device("cuda:0")
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+
+
+def gpu_aa_run(prob, m, variant, iters, flags=0, x0=None, record=True):
+    """Run AA on the GPU with the library's stencil map; returns the iterates
+    x_0..x_{iters+1} (numpy) and the context."""
+    import torch
+    from paper_2110_09667_amd import aa
+    dev = torch.device("cuda:0")
+    n = prob.n
+    f_d = to_dev(prob.f)
+    ctx = aa.AAContext(n, m, variant, flags)
+    x = to_dev(np.zeros(n) if x0 is None else x0)
+    g = torch.empty_like(x)
+    xs = [x.cpu().numpy()]
+    for _ in range(iters + 1):
+        aa.aa_problem_apply(prob.d, prob.s, prob.h, prob.omega, prob.c, f_d, x, g)
+        ctx.step(x, g, x)
+        if record:
+            xs.append(x.cpu().numpy())
+    torch.cuda.synchronize(dev)
+    return xs, ctx
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
