@@ -44,7 +44,7 @@ def run_variant(prob, m, variant, steps, warmup, grid=None, profile=True):
 
     n = prob.n
     dev = torch.device("cuda:0")
-    f_d = torch.from_numpy(prob.f).to(dev)
+    f_d = device_rhs(prob)
     ctx = aa.AAContext(n, m, variant)
     if grid:
         ctx.set_grid(*grid)
@@ -93,6 +93,28 @@ def run_variant(prob, m, variant, steps, warmup, grid=None, profile=True):
     del x, g, f_d
     torch.cuda.empty_cache()
     return out
+
+
+def device_rhs(prob):
+    """f ~ U[0, 1] of the 3D workload (seed 2, stream 0), generated on the GPU
+    by the library's generator (bit-identical to aa_workloads.uniform)."""
+    import torch
+    from paper_2110_09667_amd import aa
+    import aa_workloads as W
+    f = torch.empty(prob.n, dtype=torch.float64, device="cuda:0")
+    aa.aa_fill_uniform(f, W.SEED_POISSON3D_F, 0)
+    return f
+
+
+class Problem3D:
+    """Parameters of G(u) = u - omega (A u + u^3 - f) on an s^3 grid (f on device)."""
+
+    def __init__(self, s):
+        import aa_workloads as W
+        self.d, self.s, self.c = 3, s, 1.0
+        self.n = s ** 3
+        self.h = 1.0 / (s + 1)
+        self.omega = 0.9 / W.laplacian_lambda_max(3, s)
 
 
 def cpu_baseline(m, variant, s=128, timed_steps=3):
@@ -179,7 +201,7 @@ def main():
         __graft_entry__.build()
     aa.lib()
 
-    prob = W.nonlinear3d(s=args.s)
+    prob = Problem3D(args.s)
     print(f"# workload: 3D nonlinear, s={args.s}, n={prob.n}, m={args.m}", file=sys.stderr,
           flush=True)
     main_res = run_variant(prob, args.m, args.variant, args.steps, args.warmup, args.grid)

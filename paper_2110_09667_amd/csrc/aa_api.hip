@@ -43,6 +43,9 @@ struct aa_ctx {
 namespace {
 
 constexpr size_t kAlign = 256;
+// Reduction partials: room for kMaxRed values from 4096 workgroups (the
+// largest streaming grid), which also covers the Gram pass below.
+constexpr size_t kPartials = (size_t)kMaxRed * 4096;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -83,8 +86,7 @@ Layout make_layout(int64_t n, int m, unsigned flags) {
   L.off_scal = o; o = align_up(o + sizeof(double) * S_COUNT);
   L.off_status = o; o = align_up(o + sizeof(int));
   L.off_ticket = o; o = align_up(o + sizeof(unsigned));
-  const size_t part = (size_t)kMaxRed * 1024 > (size_t)kMaxPairs * 256
-                          ? (size_t)kMaxRed * 1024 : (size_t)kMaxPairs * 256;
+  const size_t part = kPartials;
   L.off_part = o; o = align_up(o + sizeof(double) * part);
   L.total = o;
   return L;
@@ -532,9 +534,9 @@ aa_status aa_profile_read(aa_ctx* c, int kind, double* ms, int64_t* launches, do
 aa_status aa_set_grid(aa_ctx* c, int stream_max, int gram_max) {
   if (!c || stream_max < 1 || stream_max > 4096 || gram_max < 1 || gram_max > 4096)
     return AA_EINVAL;
-  // the partials buffer holds kMaxRed x 1024 and kMaxPairs x 256 values
-  if ((size_t)stream_max * kMaxRed > (size_t)kMaxRed * 1024 ||
-      (size_t)gram_max * kMaxPairs > (size_t)kMaxPairs * 256)
+  // every pass publishes (values reduced) x (workgroups) partials
+  const size_t gram_vals = (size_t)(c->m - 1) * (c->m - 2) / 2 + 1;
+  if ((size_t)stream_max * kMaxRed > kPartials || (size_t)gram_max * gram_vals > kPartials)
     return AA_EINVAL;
   c->grid_stream_max = stream_max;
   c->grid_gram_max = gram_max;

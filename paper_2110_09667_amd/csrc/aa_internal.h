@@ -11,8 +11,8 @@ namespace aa {
 
 constexpr int kWG = 256;             // threads per workgroup (4 wave64s)
 constexpr int kWaves = kWG / 64;
-constexpr int kRPT = 8;              // rows per thread per tile in streaming passes
-constexpr int kTile = kWG * kRPT;    // rows per tile in streaming passes
+constexpr int kPairs = 4;            // row pairs (16-byte loads) per lane per tile
+constexpr int kTile = kWG * 2 * kPairs;  // rows per tile in streaming passes
 constexpr int kMaxCols = AA_MAX_COLS;
 constexpr int kMaxRed = 2 * kMaxCols + 4;  // reductions of one streaming pass
 constexpr int kMaxPairs = (kMaxCols - 1) * (kMaxCols - 2) / 2;  // Gram after delete

@@ -11,6 +11,8 @@
 // bitwise reproducible for a given grid, and no value crosses to the host.
 #include <math.h>
 
+#include <type_traits>
+
 #include "aa_internal.h"
 
 namespace aa {
@@ -213,32 +215,78 @@ __device__ void finish(const Small& sm, const Tail& t, int nred, const double* a
 }
 
 // ---------------------------------------------------------------------------
-// row loads for the streaming passes (kRPT rows per thread, stride kWG)
+// row loads for the streaming passes: each lane owns kPairs pairs of
+// consecutive rows (16-byte loads), pair i at rows b2 + 2 i kWG + {0, 1}
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void load_rows(double (&r)[kRPT], const double* __restrict__ p,
-                                          int64_t base, int64_t n, bool full) {
+template <bool FULL>
+__device__ __forceinline__ void ld2(double2 (&r)[kPairs], const double* __restrict__ p,
+                                    int64_t b2, int64_t n) {
 #pragma unroll
-  for (int i = 0; i < kRPT; ++i) {
-    const int64_t row = base + (int64_t)i * kWG;
-    r[i] = (full || row < n) ? p[row] : 0.0;
+  for (int i = 0; i < kPairs; ++i) {
+    const int64_t row = b2 + (int64_t)i * 2 * kWG;
+    if (FULL) {
+      r[i] = *reinterpret_cast<const double2*>(p + row);
+    } else {
+      r[i].x = row < n ? p[row] : 0.0;
+      r[i].y = row + 1 < n ? p[row + 1] : 0.0;
+    }
   }
 }
 
-__device__ __forceinline__ void store_rows(const double (&r)[kRPT], double* p, int64_t base,
-                                           int64_t n, bool full) {
+template <bool FULL>
+__device__ __forceinline__ void st2(const double2 (&r)[kPairs], double* p, int64_t b2,
+                                    int64_t n) {
 #pragma unroll
-  for (int i = 0; i < kRPT; ++i) {
-    const int64_t row = base + (int64_t)i * kWG;
-    if (full || row < n) p[row] = r[i];
+  for (int i = 0; i < kPairs; ++i) {
+    const int64_t row = b2 + (int64_t)i * 2 * kWG;
+    if (FULL) {
+      *reinterpret_cast<double2*>(p + row) = r[i];
+    } else {
+      if (row < n) p[row] = r[i].x;
+      if (row + 1 < n) p[row + 1] = r[i].y;
+    }
   }
 }
 
-__device__ __forceinline__ double dot_rows(const double (&a)[kRPT], const double (&b)[kRPT]) {
+__device__ __forceinline__ void zero2(double2 (&r)[kPairs]) {
+#pragma unroll
+  for (int i = 0; i < kPairs; ++i) r[i] = make_double2(0.0, 0.0);
+}
+
+__device__ __forceinline__ double dot2(const double2 (&a)[kPairs], const double2 (&b)[kPairs]) {
   double s = 0.0;
 #pragma unroll
-  for (int i = 0; i < kRPT; ++i) s = fma(a[i], b[i], s);
+  for (int i = 0; i < kPairs; ++i) {
+    s = fma(a[i].x, b[i].x, s);
+    s = fma(a[i].y, b[i].y, s);
+  }
   return s;
+}
+
+// acc += q * c
+__device__ __forceinline__ void axpy2(double2 (&acc)[kPairs], const double2 (&q)[kPairs],
+                                      double c) {
+#pragma unroll
+  for (int i = 0; i < kPairs; ++i) {
+    acc[i].x = fma(q[i].x, c, acc[i].x);
+    acc[i].y = fma(q[i].y, c, acc[i].y);
+  }
+}
+
+constexpr int kGroup = 4;  // Q columns loaded together (kGroup * kPairs loads in flight)
+
+// Visit the tiles of this workgroup: full tiles take the unmasked body.
+template <class Body>
+__device__ __forceinline__ void for_tiles(int64_t n, Body&& body) {
+  const int64_t ntiles = (n + kTile - 1) / kTile;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t b2 = tile * kTile + 2 * (int64_t)threadIdx.x;
+    if ((tile + 1) * kTile <= n)
+      body(b2, std::true_type{});
+    else
+      body(b2, std::false_type{});
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -254,36 +302,78 @@ __global__ __launch_bounds__(kWG) void k_dots(DotsArgs a, Small sm, Tail t) {
   for (int c = threadIdx.x; c < kWaves * kMaxRed; c += kWG) s_acc[c] = 0.0;
   __syncthreads();
   double* acc = s_acc + w * kMaxRed;
-  const int64_t ntiles = (a.n + kTile - 1) / kTile;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t base = tile * kTile + threadIdx.x;
-    const bool full = (tile + 1) * kTile <= a.n;
-    double xv[kRPT], yv[kRPT];
-    load_rows(xv, a.x, base, a.n, full);
-    if (a.ny > 0) load_rows(yv, a.y, base, a.n, full);
+  for_tiles(a.n, [&](int64_t b2, auto full) {
+    constexpr bool F = decltype(full)::value;
+    double2 xv[kPairs], yv[kPairs];
+    ld2<F>(xv, a.x, b2, a.n);
+    if (a.ny > 0) ld2<F>(yv, a.y, b2, a.n);
     if (a.xx) {
-      const double p = wave_sum(dot_rows(xv, xv));
+      const double p = wave_sum(dot2(xv, xv));
       if (lane == 0) acc[a.nx + a.ny] += p;
     }
-    for (int j = 0; j < nq; ++j) {
-      double qv[kRPT];
-      load_rows(qv, a.Q + (int64_t)j * a.ldq, base, a.n, full);
-      if (j < a.nx) {
-        const double p = wave_sum(dot_rows(qv, xv));
-        if (lane == 0) acc[j] += p;
+    for (int j0 = 0; j0 < nq; j0 += kGroup) {
+      double2 q[kGroup][kPairs];
+#pragma unroll
+      for (int c = 0; c < kGroup; ++c) {
+        if (j0 + c < nq)
+          ld2<F>(q[c], a.Q + (int64_t)(j0 + c) * a.ldq, b2, a.n);
+        else
+          zero2(q[c]);
       }
-      if (j < a.ny) {
-        const double p = wave_sum(dot_rows(qv, yv));
-        if (lane == 0) acc[a.nx + j] += p;
+      if (a.ny > 0) {
+        double v[2 * kGroup];
+#pragma unroll
+        for (int c = 0; c < kGroup; ++c) {
+          v[c] = (j0 + c < a.nx) ? dot2(q[c], xv) : 0.0;
+          v[kGroup + c] = (j0 + c < a.ny) ? dot2(q[c], yv) : 0.0;
+        }
+        const double r = multi_reduce<2 * kGroup>(v);
+        if (lane < kGroup) {
+          if (j0 + lane < a.nx) acc[j0 + lane] += r;
+        } else if (lane < 2 * kGroup) {
+          const int j = j0 + lane - kGroup;
+          if (j < a.ny) acc[a.nx + j] += r;
+        }
+      } else {
+        double v[kGroup];
+#pragma unroll
+        for (int c = 0; c < kGroup; ++c) v[c] = (j0 + c < a.nx) ? dot2(q[c], xv) : 0.0;
+        const double r = multi_reduce<kGroup>(v);
+        if (lane < kGroup && j0 + lane < a.nx) acc[j0 + lane] += r;
       }
     }
-  }
+  });
   finish(sm, t, nred, s_acc, kMaxRed, s_red);
 }
 
 // ---------------------------------------------------------------------------
 // vector update out = v - Q c (+ fused dot / norm); DCGS-2 reorthogonalization
 // ---------------------------------------------------------------------------
+
+// acc1 += sum_{j in [j0, j1)} Q_j c1[j], acc2 += sum Q_j c2[j] (c2 may be null)
+template <bool F>
+__device__ __forceinline__ void combine_cols(const double* __restrict__ Q, int64_t ldq,
+                                             int64_t b2, int64_t n, int j0, int j1,
+                                             const double* c1, const double* c2,
+                                             double2 (&acc1)[kPairs], double2 (&acc2)[kPairs]) {
+  for (int g = j0; g < j1; g += kGroup) {
+    double2 q[kGroup][kPairs];
+#pragma unroll
+    for (int c = 0; c < kGroup; ++c) {
+      if (g + c < j1)
+        ld2<F>(q[c], Q + (int64_t)(g + c) * ldq, b2, n);
+      else
+        zero2(q[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < kGroup; ++c) {
+      if (g + c < j1) {
+        axpy2(acc1, q[c], c1[g + c]);
+        if (c2) axpy2(acc2, q[c], c2[g + c]);
+      }
+    }
+  }
+}
 
 __global__ __launch_bounds__(kWG) void k_update(UpdArgs a, Small sm, Tail t) {
   __shared__ double s_c1[kMaxCols], s_c2[kMaxCols], s_s[kMaxCols];
@@ -299,65 +389,52 @@ __global__ __launch_bounds__(kWG) void k_update(UpdArgs a, Small sm, Tail t) {
   __syncthreads();
   const int nred = (a.dotcol >= 0 ? 1 : 0) + (a.nrm ? 1 : 0);
   const int inorm = a.dotcol >= 0 ? 1 : 0;
-  const int64_t ntiles = (a.n + kTile - 1) / kTile;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t base = tile * kTile + threadIdx.x;
-    const bool full = (tile + 1) * kTile <= a.n;
-    double o[kRPT], acc1[kRPT], acc2[kRPT];
-    load_rows(o, a.v, base, a.n, full);
-#pragma unroll
-    for (int i = 0; i < kRPT; ++i) acc1[i] = acc2[i] = 0.0;
+  const double* c2 = a.c2 ? s_c2 : nullptr;
+  for_tiles(a.n, [&](int64_t b2, auto full) {
+    constexpr bool F = decltype(full)::value;
+    double2 o[kPairs], dq[kPairs], acc1[kPairs], acc2[kPairs];
+    ld2<F>(o, a.v, b2, a.n);
+    if (a.dotcol >= 0) ld2<F>(dq, a.Q + (int64_t)a.dotcol * a.ldq, b2, a.n);
+    zero2(acc1);
+    zero2(acc2);
     if (a.dcgs2_p >= 0) {
       // Alg. 6: q'_p = q_p - Q_{:,0:p-1} s, then v - Q_{:,0:p-1} c - q'_p c_p
       const int p = a.dcgs2_p;
-#pragma unroll 2
-      for (int j = 0; j < p; ++j) {
-        double qv[kRPT];
-        load_rows(qv, a.Q + (int64_t)j * a.ldq, base, a.n, full);
-        const double cj = s_c1[j], sj = s_s[j];
-#pragma unroll
-        for (int i = 0; i < kRPT; ++i) {
-          acc1[i] = fma(qv[i], cj, acc1[i]);
-          acc2[i] = fma(qv[i], sj, acc2[i]);
-        }
-      }
-      double qp[kRPT];
-      load_rows(qp, a.Q + (int64_t)p * a.ldq, base, a.n, full);
+      double2 qp[kPairs];
+      ld2<F>(qp, a.Q + (int64_t)p * a.ldq, b2, a.n);
+      combine_cols<F>(a.Q, a.ldq, b2, a.n, 0, p, s_c1, a.reorth ? s_s : nullptr, acc1, acc2);
       if (a.reorth) {
 #pragma unroll
-        for (int i = 0; i < kRPT; ++i) qp[i] -= acc2[i];
-        store_rows(qp, a.Qw + (int64_t)p * a.ldq, base, a.n, full);
+        for (int i = 0; i < kPairs; ++i) {
+          qp[i].x -= acc2[i].x;
+          qp[i].y -= acc2[i].y;
+        }
+        st2<F>(qp, a.Qw + (int64_t)p * a.ldq, b2, a.n);
       }
       const double cp = s_c1[p];
 #pragma unroll
-      for (int i = 0; i < kRPT; ++i) o[i] = (o[i] - acc1[i]) - qp[i] * cp;
-    } else {
-#pragma unroll 2
-      for (int j = a.j0; j < a.j0 + a.nc; ++j) {
-        double qv[kRPT];
-        load_rows(qv, a.Q + (int64_t)j * a.ldq, base, a.n, full);
-        const double cj = s_c1[j], zj = s_c2[j];
-#pragma unroll
-        for (int i = 0; i < kRPT; ++i) {
-          acc1[i] = fma(qv[i], cj, acc1[i]);
-          acc2[i] = fma(qv[i], zj, acc2[i]);
-        }
+      for (int i = 0; i < kPairs; ++i) {
+        o[i].x = (o[i].x - acc1[i].x) - qp[i].x * cp;
+        o[i].y = (o[i].y - acc1[i].y) - qp[i].y * cp;
       }
+    } else {
+      combine_cols<F>(a.Q, a.ldq, b2, a.n, a.j0, a.j0 + a.nc, s_c1, c2, acc1, acc2);
 #pragma unroll
-      for (int i = 0; i < kRPT; ++i) o[i] = (o[i] - acc1[i]) - acc2[i];
+      for (int i = 0; i < kPairs; ++i) {
+        o[i].x = (o[i].x - acc1[i].x) - acc2[i].x;
+        o[i].y = (o[i].y - acc1[i].y) - acc2[i].y;
+      }
     }
-    if (a.out) store_rows(o, a.out, base, a.n, full);
+    if (a.out) st2<F>(o, a.out, b2, a.n);
     if (a.dotcol >= 0) {
-      double qv[kRPT];
-      load_rows(qv, a.Q + (int64_t)a.dotcol * a.ldq, base, a.n, full);
-      const double p = wave_sum(dot_rows(qv, o));
+      const double p = wave_sum(dot2(dq, o));
       if (lane == 0) s_acc[w * 4 + 0] += p;
     }
     if (a.nrm) {
-      const double p = wave_sum(dot_rows(o, o));
+      const double p = wave_sum(dot2(o, o));
       if (lane == 0) s_acc[w * 4 + inorm] += p;
     }
-  }
+  });
   finish(sm, t, nred, s_acc, 4, s_red);
 }
 
@@ -432,94 +509,128 @@ __global__ __launch_bounds__(64) void k_givens(Small sm, int k) {
       sm.R[i + (size_t)j * cap] = (i < nc && j < nc && i <= j) ? H[i + j * k] : 0.0;
 }
 
-// Pair p of the strict lower triangle in row order: p = a(a-1)/2 + b, b < a.
-constexpr int pair_a(int p) {
-  int a = 1;
-  while ((a + 1) * a / 2 <= p) ++a;
-  return a;
-}
-constexpr int pair_b(int p) { return p - pair_a(p) * (pair_a(p) - 1) / 2; }
-
-template <int KMAX, int C, int L>
-__device__ __forceinline__ void gram_fill(double (&vals)[64], const double (&q)[KMAX]) {
-  if constexpr (L < 64) {
-    constexpr int NP = (KMAX - 1) * (KMAX - 2) / 2;
-    constexpr int p = C * 64 + L;
-    if constexpr (p < NP)
-      vals[L] = q[pair_a(p)] * q[pair_b(p)];
-    else
-      vals[L] = 0.0;
-    gram_fill<KMAX, C, L + 1>(vals, q);
-  }
-}
-
-// Add the products of every pair (a, b), b < a < KMAX-1, summed over the 64
-// rows of this wave, to acc[pair]; 64 pairs per multi_reduce.
-template <int KMAX, int C>
-__device__ __forceinline__ void gram_chunks(const double (&q)[KMAX], double* acc) {
-  constexpr int NP = (KMAX - 1) * (KMAX - 2) / 2;
-  if constexpr (C * 64 < NP) {
-    double vals[64];
-    gram_fill<KMAX, C, 0>(vals, q);
-    const double r = multi_reduce<64>(vals);
-    const int lane = threadIdx.x & 63;
-    if (C * 64 + lane < NP) acc[C * 64 + lane] += r;
-    gram_chunks<KMAX, C + 1>(q, acc);
-  }
-}
-
 // Per row: x <- q_0; for j < k-1: (q_j, x) <- (c x + s q_{j+1}, -s x + c q_{j+1}).
 // The k values of the row are loaded first (registers), so the loads do not
-// wait on the stores.  ICWY (gram): the k-1 rotated values also feed the
-// strict lower Gram matrix, one pair-sum per (a, b), reduced with multi_reduce.
-template <int KMAX, bool GRAM>
+// wait on the stores.
+template <int KMAX>
+__device__ __forceinline__ void rotate_row(double (&q)[KMAX], const RotArgs& a, int64_t row,
+                                           bool valid, const double* s_c, const double* s_s) {
+  const int kk = a.k - 1;
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j)
+    q[j] = (j < a.k && valid) ? a.Q[(int64_t)j * a.ldq + row] : 0.0;
+  double x = q[0];
+#pragma unroll
+  for (int j = 0; j < KMAX - 1; ++j) {
+    if (j < kk) {
+      const double y = q[j + 1];
+      const double c = s_c[j], s = s_s[j];
+      q[j] = c * x + s * y;
+      x = -s * x + c * y;
+    }
+  }
+  if (valid) {
+#pragma unroll
+    for (int j = 0; j < KMAX - 1; ++j)
+      if (j < kk) a.Q[(int64_t)j * a.ldq + row] = q[j];
+  }
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j)
+    if (j >= kk) q[j] = 0.0;
+}
+
+template <int KMAX>
 __global__ __launch_bounds__(kWG) void k_rotate(RotArgs a, Small sm, Tail t) {
-  constexpr int NP = (KMAX - 1) * (KMAX - 2) / 2 > 0 ? (KMAX - 1) * (KMAX - 2) / 2 : 1;
-  constexpr int NPA = GRAM ? NP : 1;
   __shared__ double s_c[KMAX], s_s[KMAX];
-  __shared__ double s_acc[GRAM ? kWaves * NPA : 1];
-  __shared__ double s_red[GRAM ? NPA : 1];
+  const int cap = sm.cap;
+  for (int j = threadIdx.x; j < KMAX; j += kWG) {
+    s_c[j] = (j < a.k - 1) ? a.givens[j] : 1.0;
+    s_s[j] = (j < a.k - 1) ? a.givens[cap + j] : 0.0;
+  }
+  __syncthreads();
+  const int64_t ntiles = (a.n + kWG - 1) / kWG;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t row = tile * kWG + threadIdx.x;
+    double q[KMAX];
+    rotate_row<KMAX>(q, a, row, row < a.n, s_c, s_s);
+  }
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// ICWY after QRDelete (Sec. 3.2): rotate, then accumulate the strict lower
+// Gram matrix of the k-1 rotated columns, T_ab = q_a^T q_b (b < a).  The Gram
+// over rows is a dense contraction, done on the matrix cores: each wave stages
+// its 64 rotated rows in LDS (row stride KMAX + 1 doubles) and, 4 rows at a
+// time, issues v_mfma_f64_16x16x4 on every lower pair of 16-column blocks.
+// Operand layout of that instruction: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; lane l, register r of the result holds D[4 (l / 16) + r]
+// [l % 16].  Accumulators stay in registers across the workgroup's tiles; the
+// workgroup reduces once at the end.
+template <int KMAX>
+__global__ __launch_bounds__(kWG) void k_rotate_gram(RotArgs a, Small sm, Tail t) {
+  static_assert(KMAX % 16 == 0, "Gram blocks are 16 columns wide");
+  constexpr int KP = KMAX + 1;
+  constexpr int NB = KMAX / 16;
+  constexpr int NBP = NB * (NB + 1) / 2;
+  constexpr int NP = KMAX * (KMAX - 1) / 2;
+  constexpr int STAGE = kWaves * 64 * KP;
+  constexpr int ACC = kWaves * NP;
+  __shared__ double s_buf[STAGE > ACC ? STAGE : ACC];
+  __shared__ double s_red[NP];
+  __shared__ double s_c[KMAX], s_s[KMAX];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int cap = sm.cap;
   for (int j = threadIdx.x; j < KMAX; j += kWG) {
     s_c[j] = (j < a.k - 1) ? a.givens[j] : 1.0;
     s_s[j] = (j < a.k - 1) ? a.givens[cap + j] : 0.0;
   }
-  if (GRAM)
-    for (int c = threadIdx.x; c < kWaves * NPA; c += kWG) s_acc[c] = 0.0;
   __syncthreads();
-  const int kk = a.k - 1;
+  v4d acc[NBP];
+#pragma unroll
+  for (int p = 0; p < NBP; ++p) acc[p] = v4d{0.0, 0.0, 0.0, 0.0};
+  double* stage = s_buf + w * 64 * KP;
+  const int li = lane & 15, lk = lane >> 4;
   const int64_t ntiles = (a.n + kWG - 1) / kWG;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t row = tile * kWG + threadIdx.x;
-    const bool valid = row < a.n;
     double q[KMAX];
+    rotate_row<KMAX>(q, a, row, row < a.n, s_c, s_s);
 #pragma unroll
-    for (int j = 0; j < KMAX; ++j)
-      q[j] = (j < a.k && valid) ? a.Q[(int64_t)j * a.ldq + row] : 0.0;
-    double x = q[0];
+    for (int j = 0; j < KMAX; ++j) stage[lane * KP + j] = q[j];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 4
+    for (int r0 = 0; r0 < 64; r0 += 4) {
+      double v[NB];
 #pragma unroll
-    for (int j = 0; j < KMAX - 1; ++j) {
-      if (j < kk) {
-        const double y = q[j + 1];
-        const double c = s_c[j], s = s_s[j];
-        q[j] = c * x + s * y;
-        x = -s * x + c * y;
-      }
+      for (int b = 0; b < NB; ++b) v[b] = stage[(r0 + lk) * KP + b * 16 + li];
+      int p = 0;
+#pragma unroll
+      for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+        for (int bj = 0; bj <= bi; ++bj, ++p)
+          acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[bi], v[bj], acc[p], 0, 0, 0);
     }
-    if (valid) {
-#pragma unroll
-      for (int j = 0; j < KMAX - 1; ++j)
-        if (j < kk) a.Q[(int64_t)j * a.ldq + row] = q[j];
-    }
-    if (GRAM) {
-#pragma unroll
-      for (int j = 0; j < KMAX; ++j)
-        if (j >= kk) q[j] = 0.0;
-      gram_chunks<KMAX, 0>(q, s_acc + w * NPA);
-    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  if (GRAM) finish(sm, t, kk * (kk - 1) / 2, s_acc, NPA, s_red);
+  __syncthreads();  // staging area becomes the per-wave pair accumulators
+  double* accw = s_buf + w * NP;
+  int p = 0;
+#pragma unroll
+  for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+    for (int bj = 0; bj <= bi; ++bj, ++p)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ia = bi * 16 + 4 * lk + r, ib = bj * 16 + li;
+        if (ia > ib) accw[ia * (ia - 1) / 2 + ib] = acc[p][r];
+      }
+  const int kk = a.k - 1;
+  finish(sm, t, kk * (kk - 1) / 2, s_buf, NP, s_red);
 }
 
 // ---------------------------------------------------------------------------
@@ -528,9 +639,15 @@ __global__ __launch_bounds__(kWG) void k_rotate(RotArgs a, Small sm, Tail t) {
 
 __global__ __launch_bounds__(kWG) void k_scale(ScaleArgs a, int* status) {
   const double d = a.R[a.kk + (size_t)a.kk * a.cap];
+  const int64_t npair = a.n / 2;
   const int64_t stride = (int64_t)gridDim.x * kWG;
-  for (int64_t r = (int64_t)blockIdx.x * kWG + threadIdx.x; r < a.n; r += stride)
-    a.out[r] = a.in[r] / d;
+  const double2* in2 = reinterpret_cast<const double2*>(a.in);
+  double2* out2 = reinterpret_cast<double2*>(a.out);
+  for (int64_t r = (int64_t)blockIdx.x * kWG + threadIdx.x; r < npair; r += stride) {
+    const double2 v = in2[r];
+    out2[r] = make_double2(v.x / d, v.y / d);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (a.n & 1)) a.out[a.n - 1] = a.in[a.n - 1] / d;
 }
 
 // i >= 1 (Alg. 1): f = g - x; Delta f = f - f_prev -> W; Delta g = g - g_prev
@@ -542,39 +659,38 @@ __global__ __launch_bounds__(kWG) void k_history(HistArgs a, Small sm, Tail t) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (threadIdx.x < kWaves * 2) s_acc[threadIdx.x] = 0.0;
   __syncthreads();
-  const int64_t ntiles = (a.n + kTile - 1) / kTile;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t base = tile * kTile + threadIdx.x;
-    const bool full = (tile + 1) * kTile <= a.n;
-    double xv[kRPT], gv[kRPT], f[kRPT];
-    load_rows(xv, a.x, base, a.n, full);
-    load_rows(gv, a.g, base, a.n, full);
-#pragma unroll
-    for (int i = 0; i < kRPT; ++i) f[i] = gv[i] - xv[i];
+  for_tiles(a.n, [&](int64_t b2, auto full) {
+    constexpr bool F = decltype(full)::value;
+    double2 xv[kPairs], gv[kPairs], f[kPairs];
+    ld2<F>(xv, a.x, b2, a.n);
+    ld2<F>(gv, a.g, b2, a.n);
     if (a.first) {
-      store_rows(f, a.f_prev, base, a.n, full);
-      store_rows(gv, a.g_prev, base, a.n, full);
-      store_rows(gv, a.x_next, base, a.n, full);
-    } else {
-      double fp[kRPT], gp[kRPT];
-      load_rows(fp, a.f_prev, base, a.n, full);
-      load_rows(gp, a.g_prev, base, a.n, full);
 #pragma unroll
-      for (int i = 0; i < kRPT; ++i) {
-        fp[i] = f[i] - fp[i];
-        gp[i] = gv[i] - gp[i];
+      for (int i = 0; i < kPairs; ++i) f[i] = make_double2(gv[i].x - xv[i].x, gv[i].y - xv[i].y);
+      st2<F>(f, a.f_prev, b2, a.n);
+      st2<F>(gv, a.g_prev, b2, a.n);
+      st2<F>(gv, a.x_next, b2, a.n);
+    } else {
+      double2 fp[kPairs], gp[kPairs];
+      ld2<F>(fp, a.f_prev, b2, a.n);
+      ld2<F>(gp, a.g_prev, b2, a.n);
+#pragma unroll
+      for (int i = 0; i < kPairs; ++i) {
+        f[i] = make_double2(gv[i].x - xv[i].x, gv[i].y - xv[i].y);
+        fp[i] = make_double2(f[i].x - fp[i].x, f[i].y - fp[i].y);
+        gp[i] = make_double2(gv[i].x - gp[i].x, gv[i].y - gp[i].y);
       }
-      store_rows(fp, a.W, base, a.n, full);
-      store_rows(gp, a.dg, base, a.n, full);
-      store_rows(f, a.f_prev, base, a.n, full);
-      store_rows(gv, a.g_prev, base, a.n, full);
+      st2<F>(fp, a.W, b2, a.n);
+      st2<F>(gp, a.dg, b2, a.n);
+      st2<F>(f, a.f_prev, b2, a.n);
+      st2<F>(gv, a.g_prev, b2, a.n);
     }
-    const double p = wave_sum(dot_rows(f, f));
+    const double p = wave_sum(dot2(f, f));
     if (lane == 0) {
       s_acc[w * 2] += p;
       s_acc[w * 2 + 1] += p;  // first step: x_1 - x_0 = f_0
     }
-  }
+  });
   finish(sm, t, a.first ? 2 : 1, s_acc, 2, s_red);
 }
 
@@ -591,35 +707,38 @@ __global__ __launch_bounds__(kWG) void k_xupdate(XupdArgs a, Small sm, Tail t) {
   }
   if (threadIdx.x < kWaves) s_acc[threadIdx.x] = 0.0;
   __syncthreads();
-  const int64_t ntiles = (a.n + kTile - 1) / kTile;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t base = tile * kTile + threadIdx.x;
-    const bool full = (tile + 1) * kTile <= a.n;
-    double gv[kRPT], xv[kRPT], acc[kRPT];
-    load_rows(gv, a.g, base, a.n, full);
-    load_rows(xv, a.x, base, a.n, full);
+  for_tiles(a.n, [&](int64_t b2, auto full) {
+    constexpr bool F = decltype(full)::value;
+    double2 gv[kPairs], xv[kPairs], acc[kPairs];
+    ld2<F>(gv, a.g, b2, a.n);
+    ld2<F>(xv, a.x, b2, a.n);
+    zero2(acc);
+    for (int g0 = 0; g0 < a.mi; g0 += kGroup) {
+      double2 d[kGroup][kPairs];
 #pragma unroll
-    for (int i = 0; i < kRPT; ++i) acc[i] = 0.0;
-#pragma unroll 2
-    for (int j = 0; j < a.mi; ++j) {
-      double dv[kRPT];
-      load_rows(dv, a.ring + (int64_t)s_slot[j] * a.ldq, base, a.n, full);
-      const double gj = s_g[j];
+      for (int c = 0; c < kGroup; ++c) {
+        if (g0 + c < a.mi)
+          ld2<F>(d[c], a.ring + (int64_t)s_slot[g0 + c] * a.ldq, b2, a.n);
+        else
+          zero2(d[c]);
+      }
 #pragma unroll
-      for (int i = 0; i < kRPT; ++i) acc[i] = fma(dv[i], gj, acc[i]);
+      for (int c = 0; c < kGroup; ++c)
+        if (g0 + c < a.mi) axpy2(acc, d[c], s_g[g0 + c]);
     }
     double d2 = 0.0;
 #pragma unroll
-    for (int i = 0; i < kRPT; ++i) {
-      const double xn = gv[i] - acc[i];
-      const double d = xn - xv[i];
-      d2 = fma(d, d, d2);
+    for (int i = 0; i < kPairs; ++i) {
+      const double2 xn = make_double2(gv[i].x - acc[i].x, gv[i].y - acc[i].y);
+      const double dx = xn.x - xv[i].x, dy = xn.y - xv[i].y;
+      d2 = fma(dx, dx, d2);
+      d2 = fma(dy, dy, d2);
       gv[i] = xn;
     }
-    store_rows(gv, a.x_next, base, a.n, full);
+    st2<F>(gv, a.x_next, b2, a.n);
     const double p = wave_sum(d2);
     if (lane == 0) s_acc[w] += p;
-  }
+  });
   finish(sm, t, 1, s_acc, 1, s_red);
 }
 
@@ -659,18 +778,21 @@ static inline int kmax_bucket(int k) { return k <= 8 ? 8 : k <= 16 ? 16 : k <= 3
 
 hipError_t launch_dots(const DotsArgs& a, const Small& sm, const Tail& t, int grid,
                        hipStream_t st) {
+  (void)hipGetLastError();  // drop a stale error left by an earlier call
   hipLaunchKernelGGL(k_dots, dim3(grid), dim3(kWG), 0, st, a, sm, t);
   return hipGetLastError();
 }
 
 hipError_t launch_update(const UpdArgs& a, const Small& sm, const Tail& t, int grid,
                          hipStream_t st) {
+  (void)hipGetLastError();  // drop a stale error left by an earlier call
   hipLaunchKernelGGL(k_update, dim3(grid), dim3(kWG), 0, st, a, sm, t);
   return hipGetLastError();
 }
 
 hipError_t launch_cgs2b(const Cgs2bArgs& a, const Small& sm, const Tail& t, int grid,
                         hipStream_t st) {
+  (void)hipGetLastError();  // drop a stale error left by an earlier call
   switch (kmax_bucket(a.k)) {
     case 8: hipLaunchKernelGGL(k_cgs2b<8>, dim3(grid), dim3(kWG), 0, st, a, sm, t); break;
     case 16: hipLaunchKernelGGL(k_cgs2b<16>, dim3(grid), dim3(kWG), 0, st, a, sm, t); break;
@@ -681,34 +803,40 @@ hipError_t launch_cgs2b(const Cgs2bArgs& a, const Small& sm, const Tail& t, int 
 }
 
 hipError_t launch_givens(const Small& sm, int k, hipStream_t st) {
+  (void)hipGetLastError();  // drop a stale error left by an earlier call
   hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, sm, k);
   return hipGetLastError();
 }
 
 hipError_t launch_rotate(const RotArgs& a, const Small& sm, const Tail& t, int grid,
                          hipStream_t st) {
-  const int b = a.k <= 8 ? 8 : a.k <= 16 ? 16 : a.k <= 32 ? 32 : a.k <= 64 ? 64 : 65;
+  (void)hipGetLastError();  // drop a stale error left by an earlier call
   if (a.gram) {
-    switch (b) {
-      case 8: hipLaunchKernelGGL((k_rotate<8, true>), dim3(grid), dim3(kWG), 0, st, a, sm, t); break;
-      case 16: hipLaunchKernelGGL((k_rotate<16, true>), dim3(grid), dim3(kWG), 0, st, a, sm, t); break;
-      case 32: hipLaunchKernelGGL((k_rotate<32, true>), dim3(grid), dim3(kWG), 0, st, a, sm, t); break;
-      case 64: hipLaunchKernelGGL((k_rotate<64, true>), dim3(grid), dim3(kWG), 0, st, a, sm, t); break;
-      default: return hipErrorInvalidValue;  // ICWY window limited to 64
-    }
+    if (a.k <= 16)
+      hipLaunchKernelGGL(k_rotate_gram<16>, dim3(grid), dim3(kWG), 0, st, a, sm, t);
+    else if (a.k <= 32)
+      hipLaunchKernelGGL(k_rotate_gram<32>, dim3(grid), dim3(kWG), 0, st, a, sm, t);
+    else if (a.k <= 64)
+      hipLaunchKernelGGL(k_rotate_gram<64>, dim3(grid), dim3(kWG), 0, st, a, sm, t);
+    else
+      return hipErrorInvalidValue;  // the ICWY window is limited to 64 columns
   } else {
-    switch (b) {
-      case 8: hipLaunchKernelGGL((k_rotate<8, false>), dim3(grid), dim3(kWG), 0, st, a, sm, t); break;
-      case 16: hipLaunchKernelGGL((k_rotate<16, false>), dim3(grid), dim3(kWG), 0, st, a, sm, t); break;
-      case 32: hipLaunchKernelGGL((k_rotate<32, false>), dim3(grid), dim3(kWG), 0, st, a, sm, t); break;
-      case 64: hipLaunchKernelGGL((k_rotate<64, false>), dim3(grid), dim3(kWG), 0, st, a, sm, t); break;
-      default: hipLaunchKernelGGL((k_rotate<65, false>), dim3(grid), dim3(kWG), 0, st, a, sm, t); break;
-    }
+    if (a.k <= 8)
+      hipLaunchKernelGGL(k_rotate<8>, dim3(grid), dim3(kWG), 0, st, a, sm, t);
+    else if (a.k <= 16)
+      hipLaunchKernelGGL(k_rotate<16>, dim3(grid), dim3(kWG), 0, st, a, sm, t);
+    else if (a.k <= 32)
+      hipLaunchKernelGGL(k_rotate<32>, dim3(grid), dim3(kWG), 0, st, a, sm, t);
+    else if (a.k <= 64)
+      hipLaunchKernelGGL(k_rotate<64>, dim3(grid), dim3(kWG), 0, st, a, sm, t);
+    else
+      hipLaunchKernelGGL(k_rotate<65>, dim3(grid), dim3(kWG), 0, st, a, sm, t);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_scale(const ScaleArgs& a, const Small& sm, hipStream_t st) {
+  (void)hipGetLastError();  // drop a stale error left by an earlier call
   int64_t blocks = (a.n + kWG - 1) / kWG;
   int grid = (int)(blocks < 4096 ? blocks : 4096);
   hipLaunchKernelGGL(k_scale, dim3(grid), dim3(kWG), 0, st, a, sm.status);
@@ -717,22 +845,26 @@ hipError_t launch_scale(const ScaleArgs& a, const Small& sm, hipStream_t st) {
 
 hipError_t launch_history(const HistArgs& a, const Small& sm, const Tail& t, int grid,
                           hipStream_t st) {
+  (void)hipGetLastError();  // drop a stale error left by an earlier call
   hipLaunchKernelGGL(k_history, dim3(grid), dim3(kWG), 0, st, a, sm, t);
   return hipGetLastError();
 }
 
 hipError_t launch_xupdate(const XupdArgs& a, const Small& sm, const Tail& t, int grid,
                           hipStream_t st) {
+  (void)hipGetLastError();  // drop a stale error left by an earlier call
   hipLaunchKernelGGL(k_xupdate, dim3(grid), dim3(kWG), 0, st, a, sm, t);
   return hipGetLastError();
 }
 
 hipError_t launch_init_small(const Small& sm, hipStream_t st) {
+  (void)hipGetLastError();  // drop a stale error left by an earlier call
   hipLaunchKernelGGL(k_init_small, dim3(8), dim3(kWG), 0, st, sm);
   return hipGetLastError();
 }
 
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t st) {
+  (void)hipGetLastError();  // drop a stale error left by an earlier call
   int64_t blocks = (n + kWG - 1) / kWG;
   int grid = (int)(blocks < 4096 ? blocks : 4096);
   if (grid < 1) grid = 1;

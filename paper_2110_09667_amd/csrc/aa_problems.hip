@@ -38,6 +38,7 @@ __global__ __launch_bounds__(256) void k_stencil(int dim, int64_t s, double ih2,
 
 hipError_t launch_stencil(int dim, int64_t s, double h, double omega, double c,
                           const double* f, const double* u, double* out, hipStream_t st) {
+  (void)hipGetLastError();  // drop a stale error left by an earlier call
   int64_t n = s;
   if (dim >= 2) n *= s;
   if (dim >= 3) n *= s;
@@ -90,6 +91,7 @@ __global__ void k_fill_normal(double* out, int64_t n, uint64_t base, uint64_t of
 
 hipError_t launch_fill_uniform(double* out, int64_t n, uint64_t seed, uint64_t stream_id,
                                uint64_t offset, double lo, double hi, hipStream_t st) {
+  (void)hipGetLastError();  // drop a stale error left by an earlier call
   int64_t blocks = (n + 255) / 256;
   int grid = (int)(blocks < 65536 ? blocks : 65536);
   if (grid < 1) grid = 1;
@@ -100,6 +102,7 @@ hipError_t launch_fill_uniform(double* out, int64_t n, uint64_t seed, uint64_t s
 
 hipError_t launch_fill_normal(double* out, int64_t n, uint64_t seed, uint64_t stream_id,
                               uint64_t offset, hipStream_t st) {
+  (void)hipGetLastError();  // drop a stale error left by an earlier call
   int64_t blocks = (n + 255) / 256;
   int grid = (int)(blocks < 65536 ? blocks : 65536);
   if (grid < 1) grid = 1;
