@@ -61,7 +61,7 @@ int64_t leading_dim(int64_t n) {
 struct Layout {
   int64_t ldq;
   size_t off_Q, off_ring, off_W, off_fp, off_gp, off_R, off_T, off_c0, off_c1, off_gam,
-      off_giv, off_scal, off_status, off_ticket, off_part, total;
+      off_giv, off_scal, off_status, off_part, total;
 };
 
 Layout make_layout(int64_t n, int m, unsigned flags) {
@@ -85,7 +85,6 @@ Layout make_layout(int64_t n, int m, unsigned flags) {
   L.off_giv = o; o = align_up(o + sizeof(double) * 2 * cap);
   L.off_scal = o; o = align_up(o + sizeof(double) * S_COUNT);
   L.off_status = o; o = align_up(o + sizeof(int));
-  L.off_ticket = o; o = align_up(o + sizeof(unsigned));
   const size_t part = kPartials;
   L.off_part = o; o = align_up(o + sizeof(double) * part);
   L.total = o;
@@ -331,7 +330,6 @@ aa_status aa_init(aa_ctx** ctx, int64_t n, int m, int variant, unsigned flags,
   c->sm.givens = (double*)(base + L.off_giv);
   c->sm.scal = (double*)(base + L.off_scal);
   c->sm.status = (int*)(base + L.off_status);
-  c->sm.ticket = (unsigned*)(base + L.off_ticket);
   c->sm.partials = (double*)(base + L.off_part);
   c->sm.cap = m;
   if (launch_init_small(c->sm, c->stream) != hipSuccess) {

@@ -16,6 +16,8 @@ constexpr int kTile = kWG * 2 * kPairs;  // rows per tile in streaming passes
 constexpr int kMaxCols = AA_MAX_COLS;
 constexpr int kMaxRed = 2 * kMaxCols + 4;  // reductions of one streaming pass
 constexpr int kMaxPairs = (kMaxCols - 1) * (kMaxCols - 2) / 2;  // Gram after delete
+constexpr int kMaxRedAll = kMaxPairs > kMaxRed ? kMaxPairs : kMaxRed;
+constexpr int kFinWG = 1024;         // threads of the finalize kernel
 
 // Scalar slots in the small device block.
 enum Scal : int { S_RES = 0, S_RES0 = 1, S_STEP = 2, S_COUNT = 8 };
@@ -48,7 +50,6 @@ struct Small {
   double* scal;     // S_COUNT scalars
   int* status;      // latched aa_status
   double* partials; // reduction partials, [nred][grid]
-  unsigned* ticket; // arrival counter of the last-workgroup reduction
   int cap;
 };
 

@@ -5,10 +5,10 @@
 // leading dimension) from HBM once per pass.  A "Sync" of the paper -- a
 // global reduction -- is one kernel: each workgroup folds its rows into
 // per-wave partial sums in LDS, publishes one partial per reduced value, and
-// the last workgroup to arrive (atomic ticket) sums the partials in a fixed
-// order and runs the small dense tail on the device (R and T updates, the T
-// solve of ICWY, the back substitution for gamma).  Results are therefore
-// bitwise reproducible for a given grid, and no value crosses to the host.
+// a one-workgroup finalize kernel sums the partials in a fixed order and runs
+// the small dense tail on the device (R and T updates, the T solve of ICWY,
+// the back substitution for gamma).  Results are therefore bitwise
+// reproducible for a given grid, and no value crosses to the host.
 #include <math.h>
 
 #include <type_traits>
@@ -61,49 +61,16 @@ __device__ __forceinline__ double multi_reduce(double (&v)[N]) {
 // grid-wide reduction by the last-arriving workgroup, and the dense tails
 // ---------------------------------------------------------------------------
 
-// Publish this workgroup's nred values; return true in the last workgroup.
-__device__ bool arrive(const Small& sm, int nred, const double* wg_vals) {
-  const int G = gridDim.x, b = blockIdx.x;
-  for (int c = threadIdx.x; c < nred; c += kWG) sm.partials[(size_t)c * G + b] = wg_vals[c];
-  __threadfence();
-  __syncthreads();
-  __shared__ int s_last;
-  if (threadIdx.x == 0) {
-    unsigned prev = __hip_atomic_fetch_add(sm.ticket, 1u, __ATOMIC_ACQ_REL,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (prev == (unsigned)(G - 1));
-  }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  return true;
-}
-
-// Fixed-order sum of the partials into red[] (LDS), then reset the ticket.
-__device__ void collect(const Small& sm, int nred, double* red) {
-  const int G = gridDim.x;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int c = w; c < nred; c += kWaves) {
-    const double* p = sm.partials + (size_t)c * G;
-    double s = 0.0;
-    for (int g = lane; g < G; g += 64) s += p[g];
-    s = wave_sum(s);
-    if (lane == 0) red[c] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0)
-    __hip_atomic_store(sm.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __device__ void run_tail(const Small& sm, const Tail& t, const double* red) {
   const int tid = threadIdx.x, lane = tid & 63;
+  const int nthr = blockDim.x;
   const int cap = sm.cap;
   double* R = sm.R;
   double* T = sm.T;
   const int k = t.k;
   switch (t.op) {
     case TAIL_STORE:
-      for (int i = tid; i < t.count; i += kWG) sm.coef0[i] = red[i];
+      for (int i = tid; i < t.count; i += nthr) sm.coef0[i] = red[i];
       break;
     case TAIL_MGS_R:
       if (tid == 0) R[t.row + (size_t)k * cap] = red[0];
@@ -116,10 +83,10 @@ __device__ void run_tail(const Small& sm, const Tail& t, const double* red) {
       }
       break;
     case TAIL_CGS2_S:
-      for (int i = tid; i < k; i += kWG) sm.coef0[i] = red[i];
+      for (int i = tid; i < k; i += nthr) sm.coef0[i] = red[i];
       break;
     case TAIL_CGS2_Z:
-      for (int i = tid; i < k; i += kWG) {
+      for (int i = tid; i < k; i += nthr) {
         sm.coef1[i] = red[i];
         R[i + (size_t)k * cap] = sm.coef0[i] + red[i];
       }
@@ -129,7 +96,7 @@ __device__ void run_tail(const Small& sm, const Tail& t, const double* red) {
       // unit lower triangular T r' = r with r = red[0:k] (forward
       // substitution, one lane per row); r' is column k of R and the
       // coefficients of the update pass.
-      for (int b = tid; b < k - 1; b += kWG) T[(k - 1) + (size_t)b * cap] = red[k + b];
+      for (int b = tid; b < k - 1; b += nthr) T[(k - 1) + (size_t)b * cap] = red[k + b];
       if (tid < 64) {
         double x = (lane < k) ? red[lane] : 0.0;
         for (int b = 0; b < k; ++b) {
@@ -149,11 +116,11 @@ __device__ void run_tail(const Small& sm, const Tail& t, const double* red) {
       // Alg. 6: column k of R is Q^T v computed with the old q_{k-1}; with
       // reorthogonalization s = red[k:2k-1] corrects column k-1 of R so that
       // Q R = F_i keeps holding after q_{k-1} -= Q_{:,0:k-2} s.
-      for (int i = tid; i < k; i += kWG) R[i + (size_t)k * cap] = red[i];
+      for (int i = tid; i < k; i += nthr) R[i + (size_t)k * cap] = red[i];
       if (t.reorth) {
         const int p = k - 1;
         const double scale = t.literal ? 1.0 : R[p + (size_t)p * cap];
-        for (int i = tid; i < p; i += kWG) {
+        for (int i = tid; i < p; i += nthr) {
           const double s = red[k + i];
           sm.coef1[i] = s;
           R[i + (size_t)p * cap] += scale * s;
@@ -189,7 +156,7 @@ __device__ void run_tail(const Small& sm, const Tail& t, const double* red) {
     case TAIL_GRAM: {
       // ICWY after QRDelete: T_ab = q_a^T q_b (b < a < k), pair a(a-1)/2 + b.
       for (int a = 1; a < k; ++a)
-        for (int b = tid; b < a; b += kWG) T[a + (size_t)b * cap] = red[a * (a - 1) / 2 + b];
+        for (int b = tid; b < a; b += nthr) T[a + (size_t)b * cap] = red[a * (a - 1) / 2 + b];
       break;
     }
     default:
@@ -197,20 +164,35 @@ __device__ void run_tail(const Small& sm, const Tail& t, const double* red) {
   }
 }
 
-// Combine the per-wave accumulators of this workgroup, then reduce across the
-// grid; the last workgroup runs the tail.
-__device__ void finish(const Small& sm, const Tail& t, int nred, const double* acc,
-                       int acc_stride, double* red) {
+// Combine the per-wave accumulators of this workgroup and publish them as this
+// workgroup's entries of the partials ([value][workgroup]); k_finalize, the
+// next kernel on the stream, reduces them (the kernel boundary orders the
+// writes before the reads, so no fence or atomic is needed here).
+__device__ void finish(const Small& sm, int nred, const double* acc, int acc_stride) {
   __syncthreads();
+  const int G = gridDim.x, b = blockIdx.x;
   for (int c = threadIdx.x; c < nred; c += kWG) {
     double s = acc[c];
 #pragma unroll
     for (int w = 1; w < kWaves; ++w) s += acc[w * acc_stride + c];
-    red[c] = s;
+    sm.partials[(size_t)c * G + b] = s;
+  }
+}
+
+// Fixed-order sum of the G partials of each of the nred values (one wave per
+// value, lanes strided over the workgroups), then the dense tail.
+__global__ __launch_bounds__(kFinWG) void k_finalize(Small sm, Tail t, int nred, int G) {
+  __shared__ double red[kMaxRedAll];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int waves = kFinWG / 64;
+  for (int c = w; c < nred; c += waves) {
+    const double* p = sm.partials + (size_t)c * G;
+    double s = 0.0;
+    for (int g = lane; g < G; g += 64) s += p[g];
+    s = wave_sum(s);
+    if (lane == 0) red[c] = s;
   }
   __syncthreads();
-  if (!arrive(sm, nred, red)) return;
-  collect(sm, nred, red);
   run_tail(sm, t, red);
 }
 
@@ -295,7 +277,6 @@ __device__ __forceinline__ void for_tiles(int64_t n, Body&& body) {
 
 __global__ __launch_bounds__(kWG) void k_dots(DotsArgs a, Small sm, Tail t) {
   __shared__ double s_acc[kWaves * kMaxRed];
-  __shared__ double s_red[kMaxRed];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int nq = a.nx > a.ny ? a.nx : a.ny;
   const int nred = a.nx + a.ny + (a.xx ? 1 : 0);
@@ -343,7 +324,7 @@ __global__ __launch_bounds__(kWG) void k_dots(DotsArgs a, Small sm, Tail t) {
       }
     }
   });
-  finish(sm, t, nred, s_acc, kMaxRed, s_red);
+  finish(sm, nred, s_acc, kMaxRed);
 }
 
 // ---------------------------------------------------------------------------
@@ -378,7 +359,6 @@ __device__ __forceinline__ void combine_cols(const double* __restrict__ Q, int64
 __global__ __launch_bounds__(kWG) void k_update(UpdArgs a, Small sm, Tail t) {
   __shared__ double s_c1[kMaxCols], s_c2[kMaxCols], s_s[kMaxCols];
   __shared__ double s_acc[kWaves * 4];
-  __shared__ double s_red[4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int j = threadIdx.x; j < kMaxCols; j += kWG) {
     s_c1[j] = (a.c1 && j < a.j0 + a.nc + 1) ? a.c1[j] : 0.0;
@@ -435,7 +415,7 @@ __global__ __launch_bounds__(kWG) void k_update(UpdArgs a, Small sm, Tail t) {
       if (lane == 0) s_acc[w * 4 + inorm] += p;
     }
   });
-  finish(sm, t, nred, s_acc, 4, s_red);
+  finish(sm, nred, s_acc, 4);
 }
 
 // ---------------------------------------------------------------------------
@@ -447,7 +427,6 @@ template <int KMAX>
 __global__ __launch_bounds__(kWG) void k_cgs2b(Cgs2bArgs a, Small sm, Tail t) {
   __shared__ double s_s[KMAX];
   __shared__ double s_acc[kWaves * KMAX];
-  __shared__ double s_red[KMAX];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int j = threadIdx.x; j < KMAX; j += kWG) s_s[j] = (j < a.k) ? a.s[j] : 0.0;
   for (int c = threadIdx.x; c < kWaves * KMAX; c += kWG) s_acc[c] = 0.0;
@@ -469,7 +448,7 @@ __global__ __launch_bounds__(kWG) void k_cgs2b(Cgs2bArgs a, Small sm, Tail t) {
     const double r = multi_reduce<KMAX>(q);
     if (lane < KMAX) s_acc[w * KMAX + lane] += r;
   }
-  finish(sm, t, a.k, s_acc, KMAX, s_red);
+  finish(sm, a.k, s_acc, KMAX);
 }
 
 // ---------------------------------------------------------------------------
@@ -564,7 +543,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // its 64 rotated rows in LDS (row stride KMAX + 1 doubles) and, 4 rows at a
 // time, issues v_mfma_f64_16x16x4 on every lower pair of 16-column blocks.
 // Operand layout of that instruction: lane l supplies A[l % 16][l / 16] and
-// B[l / 16][l % 16]; lane l, register r of the result holds D[4 (l / 16) + r]
+// B[l / 16][l % 16]; lane l, register r of the result holds D[l / 16 + 4 r]
 // [l % 16].  Accumulators stay in registers across the workgroup's tiles; the
 // workgroup reduces once at the end.
 template <int KMAX>
@@ -577,7 +556,6 @@ __global__ __launch_bounds__(kWG) void k_rotate_gram(RotArgs a, Small sm, Tail t
   constexpr int STAGE = kWaves * 64 * KP;
   constexpr int ACC = kWaves * NP;
   __shared__ double s_buf[STAGE > ACC ? STAGE : ACC];
-  __shared__ double s_red[NP];
   __shared__ double s_c[KMAX], s_s[KMAX];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int cap = sm.cap;
@@ -626,11 +604,11 @@ __global__ __launch_bounds__(kWG) void k_rotate_gram(RotArgs a, Small sm, Tail t
     for (int bj = 0; bj <= bi; ++bj, ++p)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int ia = bi * 16 + 4 * lk + r, ib = bj * 16 + li;
+        const int ia = bi * 16 + lk + 4 * r, ib = bj * 16 + li;
         if (ia > ib) accw[ia * (ia - 1) / 2 + ib] = acc[p][r];
       }
   const int kk = a.k - 1;
-  finish(sm, t, kk * (kk - 1) / 2, s_buf, NP, s_red);
+  finish(sm, kk * (kk - 1) / 2, s_buf, NP);
 }
 
 // ---------------------------------------------------------------------------
@@ -655,7 +633,6 @@ __global__ __launch_bounds__(kWG) void k_scale(ScaleArgs a, int* status) {
 // i == 0: f_prev = g - x, g_prev = g, x_next = g; red = [||f||^2, ||x_1-x_0||^2].
 __global__ __launch_bounds__(kWG) void k_history(HistArgs a, Small sm, Tail t) {
   __shared__ double s_acc[kWaves * 2];
-  __shared__ double s_red[2];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (threadIdx.x < kWaves * 2) s_acc[threadIdx.x] = 0.0;
   __syncthreads();
@@ -691,7 +668,7 @@ __global__ __launch_bounds__(kWG) void k_history(HistArgs a, Small sm, Tail t) {
       s_acc[w * 2 + 1] += p;  // first step: x_1 - x_0 = f_0
     }
   });
-  finish(sm, t, a.first ? 2 : 1, s_acc, 2, s_red);
+  finish(sm, a.first ? 2 : 1, s_acc, 2);
 }
 
 // Alg. 1: x_{i+1} = g_i - sum_j gamma_j Delta g_{i-m_i+j}; red[0] = ||x_{i+1}-x_i||^2.
@@ -699,7 +676,6 @@ __global__ __launch_bounds__(kWG) void k_xupdate(XupdArgs a, Small sm, Tail t) {
   __shared__ double s_g[kMaxCols];
   __shared__ int s_slot[kMaxCols];
   __shared__ double s_acc[kWaves];
-  __shared__ double s_red[1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int j = threadIdx.x; j < a.mi; j += kWG) {
     s_g[j] = a.gamma[j];
@@ -739,7 +715,7 @@ __global__ __launch_bounds__(kWG) void k_xupdate(XupdArgs a, Small sm, Tail t) {
     const double p = wave_sum(d2);
     if (lane == 0) s_acc[w] += p;
   });
-  finish(sm, t, 1, s_acc, 1, s_red);
+  finish(sm, 1, s_acc, 1);
 }
 
 __global__ void k_init_small(Small sm) {
@@ -758,10 +734,7 @@ __global__ void k_init_small(Small sm) {
     sm.gamma[i] = 0.0;
   }
   if (blockIdx.x == 0 && threadIdx.x < S_COUNT) sm.scal[threadIdx.x] = 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    *sm.status = AA_OK;
-    *sm.ticket = 0u;
-  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *sm.status = AA_OK;
 }
 
 __global__ void k_copy(double* dst, const double* src, int64_t n) {
@@ -776,18 +749,26 @@ __global__ void k_copy(double* dst, const double* src, int64_t n) {
 
 static inline int kmax_bucket(int k) { return k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64; }
 
+static hipError_t launch_finalize(const Small& sm, const Tail& t, int nred, int grid,
+                                  hipStream_t st) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinWG), 0, st, sm, t, nred, grid);
+  return hipGetLastError();
+}
+
 hipError_t launch_dots(const DotsArgs& a, const Small& sm, const Tail& t, int grid,
                        hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
   hipLaunchKernelGGL(k_dots, dim3(grid), dim3(kWG), 0, st, a, sm, t);
-  return hipGetLastError();
+  return launch_finalize(sm, t, a.nx + a.ny + (a.xx ? 1 : 0), grid, st);
 }
 
 hipError_t launch_update(const UpdArgs& a, const Small& sm, const Tail& t, int grid,
                          hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
   hipLaunchKernelGGL(k_update, dim3(grid), dim3(kWG), 0, st, a, sm, t);
-  return hipGetLastError();
+  return launch_finalize(sm, t, (a.dotcol >= 0 ? 1 : 0) + (a.nrm ? 1 : 0), grid, st);
 }
 
 hipError_t launch_cgs2b(const Cgs2bArgs& a, const Small& sm, const Tail& t, int grid,
@@ -799,7 +780,7 @@ hipError_t launch_cgs2b(const Cgs2bArgs& a, const Small& sm, const Tail& t, int 
     case 32: hipLaunchKernelGGL(k_cgs2b<32>, dim3(grid), dim3(kWG), 0, st, a, sm, t); break;
     default: hipLaunchKernelGGL(k_cgs2b<64>, dim3(grid), dim3(kWG), 0, st, a, sm, t); break;
   }
-  return hipGetLastError();
+  return launch_finalize(sm, t, a.k, grid, st);
 }
 
 hipError_t launch_givens(const Small& sm, int k, hipStream_t st) {
@@ -820,6 +801,7 @@ hipError_t launch_rotate(const RotArgs& a, const Small& sm, const Tail& t, int g
       hipLaunchKernelGGL(k_rotate_gram<64>, dim3(grid), dim3(kWG), 0, st, a, sm, t);
     else
       return hipErrorInvalidValue;  // the ICWY window is limited to 64 columns
+    return launch_finalize(sm, t, (a.k - 1) * (a.k - 2) / 2, grid, st);
   } else {
     if (a.k <= 8)
       hipLaunchKernelGGL(k_rotate<8>, dim3(grid), dim3(kWG), 0, st, a, sm, t);
@@ -847,14 +829,14 @@ hipError_t launch_history(const HistArgs& a, const Small& sm, const Tail& t, int
                           hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
   hipLaunchKernelGGL(k_history, dim3(grid), dim3(kWG), 0, st, a, sm, t);
-  return hipGetLastError();
+  return launch_finalize(sm, t, a.first ? 2 : 1, grid, st);
 }
 
 hipError_t launch_xupdate(const XupdArgs& a, const Small& sm, const Tail& t, int grid,
                           hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
   hipLaunchKernelGGL(k_xupdate, dim3(grid), dim3(kWG), 0, st, a, sm, t);
-  return hipGetLastError();
+  return launch_finalize(sm, t, 1, grid, st);
 }
 
 hipError_t launch_init_small(const Small& sm, hipStream_t st) {

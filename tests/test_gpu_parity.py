@@ -130,6 +130,45 @@ def test_qr_add_wide_bases(variant, k):
     compare_qr(ctx, ref, 1e-11)
 
 
+@pytest.mark.parametrize("k", [5, 12, 20, 33, 47, 64])
+def test_icwy_T_refresh_on_nonorthonormal_basis(k):
+    """ICWY's T refresh after QRDelete is a Gram matrix of the rotated basis.
+    On an orthonormal basis its strict lower part is ~1e-15 everywhere, which
+    would hide a misplaced entry; an MGS basis of a kappa = 1e12 matrix has
+    lost orthogonality (~1e-4), so every entry of T is checked for real.
+    Covers the 16, 32 and 64-column Gram blocks."""
+    import torch
+    device()
+    aa = aa_mod()
+    n = 2 * 2048 + 77
+    F = graded(n, k, 1e12, seed=200 + k)
+    base = O.QR(n, k, "mgs")
+    for j in range(k):
+        base.add(F[:, j])
+    Q0, R0 = base.Qk(), base.Rk()
+    T0 = np.eye(k) + np.tril(Q0.T @ Q0, -1)
+    assert np.abs(np.tril(T0, -1)).max() > 1e-6
+    ref = O.QR(n, k, "icwy")
+    ref.Q[:, :k], ref.R[:k, :k], ref.T[:k, :k] = Q0, R0, T0
+    ref.s.k = k
+    ctx = aa.AAContext(n, k, "icwy", aa.QR_ONLY)
+    Qd = torch.from_numpy(np.ascontiguousarray(Q0.T)).cuda()  # column-major, ld = n
+    aa.aa_qr_load(ctx.ctx, k, Qd.data_ptr(), n, R0, T0)
+    compare_qr(ctx, ref, 0.0)  # loaded verbatim
+    assert ref.delete() == 0
+    ctx.qr_delete()
+    R, T, kk = ctx.get_qr()
+    assert kk == k - 1
+    Tr = ref.Tk()
+    assert np.abs(np.tril(T, -1) - np.tril(Tr, -1)).max() <= 1e-12
+    assert np.abs(R - ref.Rk()).max() <= 1e-12 * np.abs(ref.Rk()).max()
+    # and the next add uses the refreshed T
+    v = W.normal(9, k, n)
+    assert ref.add(v) == 0
+    ctx.qr_add(to_dev(v))
+    compare_qr(ctx, ref, 1e-10)
+
+
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_qr_solve_matches_oracle(variant):
     import torch
