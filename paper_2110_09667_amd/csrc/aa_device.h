@@ -1,0 +1,112 @@
+// aa_device.h -- device helpers shared by the grid-wide passes and the
+// workgroup-level (batched) passes: wavefront reductions and the 16-byte row
+// loads of the streaming passes.
+#pragma once
+
+#include "aa_internal.h"
+
+namespace aa {
+
+// ---------------------------------------------------------------------------
+// wavefront reductions
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum N per-lane values across the 64 lanes at once (N a power of two, <= 64).
+// Butterfly with halving: at the step of offset h, a lane keeps the half of
+// its values selected by lane bit h and adds its partner's copy of that half.
+// After log2(N) steps lane l holds column (l mod N) summed over the lanes that
+// share its low bits; the remaining xor steps finish the sum.  N - 1 +
+// 6 - log2(N) shuffles instead of 6 N.
+template <int H, int N>
+__device__ __forceinline__ void halve_step(double (&v)[N], int lane) {
+  if constexpr (H >= 1) {
+    const bool upper = (lane & H) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double keep = upper ? v[i + H] : v[i];
+      const double send = upper ? v[i] : v[i + H];
+      v[i] = keep + __shfl_xor(send, H, 64);
+    }
+    halve_step<H / 2, N>(v, lane);
+  }
+}
+
+template <int N>
+__device__ __forceinline__ double multi_reduce(double (&v)[N]) {
+  const int lane = threadIdx.x & 63;
+  halve_step<N / 2, N>(v, lane);
+  double r = v[0];
+#pragma unroll
+  for (int o = N; o < 64; o <<= 1) r += __shfl_xor(r, o, 64);
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// row loads for the streaming passes: each lane owns kPairs pairs of
+// consecutive rows (16-byte loads), pair i at rows b2 + 2 i kWG + {0, 1}
+// ---------------------------------------------------------------------------
+
+template <bool FULL>
+__device__ __forceinline__ void ld2(double2 (&r)[kPairs], const double* __restrict__ p,
+                                    int64_t b2, int64_t n) {
+#pragma unroll
+  for (int i = 0; i < kPairs; ++i) {
+    const int64_t row = b2 + (int64_t)i * 2 * kWG;
+    if (FULL) {
+      r[i] = *reinterpret_cast<const double2*>(p + row);
+    } else {
+      r[i].x = row < n ? p[row] : 0.0;
+      r[i].y = row + 1 < n ? p[row + 1] : 0.0;
+    }
+  }
+}
+
+template <bool FULL>
+__device__ __forceinline__ void st2(const double2 (&r)[kPairs], double* p, int64_t b2,
+                                    int64_t n) {
+#pragma unroll
+  for (int i = 0; i < kPairs; ++i) {
+    const int64_t row = b2 + (int64_t)i * 2 * kWG;
+    if (FULL) {
+      *reinterpret_cast<double2*>(p + row) = r[i];
+    } else {
+      if (row < n) p[row] = r[i].x;
+      if (row + 1 < n) p[row + 1] = r[i].y;
+    }
+  }
+}
+
+__device__ __forceinline__ void zero2(double2 (&r)[kPairs]) {
+#pragma unroll
+  for (int i = 0; i < kPairs; ++i) r[i] = make_double2(0.0, 0.0);
+}
+
+__device__ __forceinline__ double dot2(const double2 (&a)[kPairs], const double2 (&b)[kPairs]) {
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < kPairs; ++i) {
+    s = fma(a[i].x, b[i].x, s);
+    s = fma(a[i].y, b[i].y, s);
+  }
+  return s;
+}
+
+// acc += q * c
+__device__ __forceinline__ void axpy2(double2 (&acc)[kPairs], const double2 (&q)[kPairs],
+                                      double c) {
+#pragma unroll
+  for (int i = 0; i < kPairs; ++i) {
+    acc[i].x = fma(q[i].x, c, acc[i].x);
+    acc[i].y = fma(q[i].y, c, acc[i].y);
+  }
+}
+
+constexpr int kGroup = 4;  // Q columns loaded together (kGroup * kPairs loads in flight)
+
+}  // namespace aa
