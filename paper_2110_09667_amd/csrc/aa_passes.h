@@ -1,0 +1,587 @@
+// aa_passes.h -- the passes of the windowed-QR AA update as tile-range bodies,
+// shared by the grid-wide kernels (aa_kernels.hip: every workgroup takes tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ... and publishes partial sums) and the
+// workgroup-level step of the batched path (aa_batch.hip: one workgroup takes
+// every tile of one instance and reduces in LDS).  Bodies accumulate into this
+// wave's LDS accumulators; the caller zeroes them, combines the waves and runs
+// the dense tail.  Block size is kWG (4 wave64s) throughout.
+#pragma once
+
+#include <type_traits>
+
+#include "aa_device.h"
+
+namespace aa {
+
+// ---------------------------------------------------------------------------
+// dense tails, run by one workgroup once the reduced values are in red[]
+// ---------------------------------------------------------------------------
+
+__device__ inline void run_tail(const Small& sm, const Tail& t, const double* red) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int nthr = blockDim.x;
+  const int cap = sm.cap;
+  double* R = sm.R;
+  double* T = sm.T;
+  const int k = t.k;
+  switch (t.op) {
+    case TAIL_STORE:
+      for (int i = tid; i < t.count; i += nthr) sm.coef0[i] = red[i];
+      break;
+    case TAIL_MGS_R:
+      if (tid == 0) R[t.row + (size_t)k * cap] = red[0];
+      break;
+    case TAIL_NORM:
+      if (tid == 0) {
+        const double nv = sqrt(red[t.idx]);
+        R[k + (size_t)k * cap] = nv;
+        if (!(nv > 0.0) || !isfinite(nv)) *sm.status = AA_EBREAKDOWN;
+      }
+      break;
+    case TAIL_CGS2_S:
+      for (int i = tid; i < k; i += nthr) sm.coef0[i] = red[i];
+      break;
+    case TAIL_CGS2_Z:
+      for (int i = tid; i < k; i += nthr) {
+        sm.coef1[i] = red[i];
+        R[i + (size_t)k * cap] = sm.coef0[i] + red[i];
+      }
+      break;
+    case TAIL_ICWY:
+      // Alg. 4: row k-1 of T is red[k + b] (b < k-1), diagonal 1; solve the
+      // unit lower triangular T r' = r with r = red[0:k] (forward
+      // substitution, one lane per row); r' is column k of R and the
+      // coefficients of the update pass.
+      for (int b = tid; b < k - 1; b += nthr) T[(k - 1) + (size_t)b * cap] = red[k + b];
+      if (tid < 64) {
+        double x = (lane < k) ? red[lane] : 0.0;
+        for (int b = 0; b < k; ++b) {
+          const double rb = __shfl(x, b, 64);
+          if (lane > b && lane < k) {
+            const double tab = (lane == k - 1) ? red[k + b] : T[lane + (size_t)b * cap];
+            x -= tab * rb;
+          }
+        }
+        if (lane < k) {
+          R[lane + (size_t)k * cap] = x;
+          sm.coef0[lane] = x;
+        }
+      }
+      break;
+    case TAIL_DCGS2:
+      // Alg. 6: column k of R is Q^T v computed with the old q_{k-1}; with
+      // reorthogonalization s = red[k:2k-1] corrects column k-1 of R so that
+      // Q R = F_i keeps holding after q_{k-1} -= Q_{:,0:k-2} s.
+      for (int i = tid; i < k; i += nthr) R[i + (size_t)k * cap] = red[i];
+      if (t.reorth) {
+        const int p = k - 1;
+        const double scale = t.literal ? 1.0 : R[p + (size_t)p * cap];
+        for (int i = tid; i < p; i += nthr) {
+          const double s = red[k + i];
+          sm.coef1[i] = s;
+          R[i + (size_t)p * cap] += scale * s;
+        }
+      }
+      break;
+    case TAIL_RHS:
+      // Alg. 2, last line: back substitution R gamma = c, c = Q^T f_i.
+      if (tid < 64) {
+        double x = (lane < k) ? red[lane] : 0.0;
+        double gam = 0.0;
+        for (int a = k - 1; a >= 0; --a) {
+          const double ga = __shfl(x, a, 64) / R[a + (size_t)a * cap];
+          if (lane < a) x -= R[lane + (size_t)a * cap] * ga;
+          if (lane == a) gam = ga;
+        }
+        if (lane < k) sm.gamma[lane] = gam;
+      }
+      break;
+    case TAIL_RES:
+      if (tid == 0) sm.scal[S_RES] = red[0];
+      break;
+    case TAIL_FIRST:
+      if (tid == 0) {
+        sm.scal[S_RES] = red[0];
+        sm.scal[S_RES0] = red[0];
+        sm.scal[S_STEP] = red[1];
+      }
+      break;
+    case TAIL_STEP:
+      if (tid == 0) sm.scal[S_STEP] = red[0];
+      break;
+    case TAIL_GRAM: {
+      // ICWY after QRDelete: T_ab = q_a^T q_b (b < a < k), pair a(a-1)/2 + b.
+      for (int a = 1; a < k; ++a)
+        for (int b = tid; b < a; b += nthr) T[a + (size_t)b * cap] = red[a * (a - 1) / 2 + b];
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tile iteration
+// ---------------------------------------------------------------------------
+
+// Visit tiles t0, t0 + ts, ... of a streaming pass (kTile rows each); full
+// tiles take the unmasked body.
+template <class Body>
+__device__ __forceinline__ void for_tiles(int64_t n, int64_t t0, int64_t ts, Body&& body) {
+  const int64_t ntiles = (n + kTile - 1) / kTile;
+  for (int64_t tile = t0; tile < ntiles; tile += ts) {
+    const int64_t b2 = tile * kTile + 2 * (int64_t)threadIdx.x;
+    if ((tile + 1) * kTile <= n)
+      body(b2, std::true_type{});
+    else
+      body(b2, std::false_type{});
+  }
+}
+
+__device__ __forceinline__ void lds_zero(double* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// block dot products: acc_w[j] += Q_j^T x (j < nx); acc_w[nx + j] += Q_j^T y
+// (j < ny); acc_w[nx + ny] += x^T x
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int dots_nred(const DotsArgs& a) { return a.nx + a.ny + (a.xx ? 1 : 0); }
+
+__device__ inline void dots_body(const DotsArgs& a, int64_t t0, int64_t ts, double* acc) {
+  const int lane = threadIdx.x & 63;
+  const int nq = a.nx > a.ny ? a.nx : a.ny;
+  for_tiles(a.n, t0, ts, [&](int64_t b2, auto full) {
+    constexpr bool F = decltype(full)::value;
+    double2 xv[kPairs], yv[kPairs];
+    ld2<F>(xv, a.x, b2, a.n);
+    if (a.ny > 0) ld2<F>(yv, a.y, b2, a.n);
+    if (a.xx) {
+      const double p = wave_sum(dot2(xv, xv));
+      if (lane == 0) acc[a.nx + a.ny] += p;
+    }
+    for (int j0 = 0; j0 < nq; j0 += kGroup) {
+      double2 q[kGroup][kPairs];
+#pragma unroll
+      for (int c = 0; c < kGroup; ++c) {
+        if (j0 + c < nq)
+          ld2<F>(q[c], a.Q + (int64_t)(j0 + c) * a.ldq, b2, a.n);
+        else
+          zero2(q[c]);
+      }
+      if (a.ny > 0) {
+        double v[2 * kGroup];
+#pragma unroll
+        for (int c = 0; c < kGroup; ++c) {
+          v[c] = (j0 + c < a.nx) ? dot2(q[c], xv) : 0.0;
+          v[kGroup + c] = (j0 + c < a.ny) ? dot2(q[c], yv) : 0.0;
+        }
+        const double r = multi_reduce<2 * kGroup>(v);
+        if (lane < kGroup) {
+          if (j0 + lane < a.nx) acc[j0 + lane] += r;
+        } else if (lane < 2 * kGroup) {
+          const int j = j0 + lane - kGroup;
+          if (j < a.ny) acc[a.nx + j] += r;
+        }
+      } else {
+        double v[kGroup];
+#pragma unroll
+        for (int c = 0; c < kGroup; ++c) v[c] = (j0 + c < a.nx) ? dot2(q[c], xv) : 0.0;
+        const double r = multi_reduce<kGroup>(v);
+        if (lane < kGroup && j0 + lane < a.nx) acc[j0 + lane] += r;
+      }
+    }
+  });
+}
+
+// ---------------------------------------------------------------------------
+// vector update out = v - Q c (+ fused dot / norm); DCGS-2 reorthogonalization
+// acc_w[0] += Q_dotcol^T out (if dotcol >= 0); acc_w[inorm] += out^T out
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int update_nred(const UpdArgs& a) {
+  return (a.dotcol >= 0 ? 1 : 0) + (a.nrm ? 1 : 0);
+}
+
+// Coefficients of an update pass copied to LDS (read once per workgroup).
+__device__ inline void update_coefs(const UpdArgs& a, double* s_c1, double* s_c2, double* s_s) {
+  for (int j = threadIdx.x; j < kMaxCols; j += blockDim.x) {
+    s_c1[j] = (a.c1 && j < a.j0 + a.nc + 1) ? a.c1[j] : 0.0;
+    s_c2[j] = (a.c2 && j < a.j0 + a.nc) ? a.c2[j] : 0.0;
+    s_s[j] = (a.s && a.dcgs2_p >= 0 && j < a.dcgs2_p) ? a.s[j] : 0.0;
+  }
+}
+
+// acc1 += sum_{j in [j0, j1)} Q_j c1[j], acc2 += sum Q_j c2[j] (c2 may be null)
+template <bool F>
+__device__ __forceinline__ void combine_cols(const double* __restrict__ Q, int64_t ldq,
+                                             int64_t b2, int64_t n, int j0, int j1,
+                                             const double* c1, const double* c2,
+                                             double2 (&acc1)[kPairs], double2 (&acc2)[kPairs]) {
+  for (int g = j0; g < j1; g += kGroup) {
+    double2 q[kGroup][kPairs];
+#pragma unroll
+    for (int c = 0; c < kGroup; ++c) {
+      if (g + c < j1)
+        ld2<F>(q[c], Q + (int64_t)(g + c) * ldq, b2, n);
+      else
+        zero2(q[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < kGroup; ++c) {
+      if (g + c < j1) {
+        axpy2(acc1, q[c], c1[g + c]);
+        if (c2) axpy2(acc2, q[c], c2[g + c]);
+      }
+    }
+  }
+}
+
+__device__ inline void update_body(const UpdArgs& a, const double* s_c1, const double* s_c2,
+                                   const double* s_s, int64_t t0, int64_t ts, double* acc) {
+  const int lane = threadIdx.x & 63;
+  const int inorm = a.dotcol >= 0 ? 1 : 0;
+  const double* c2 = a.c2 ? s_c2 : nullptr;
+  for_tiles(a.n, t0, ts, [&](int64_t b2, auto full) {
+    constexpr bool F = decltype(full)::value;
+    double2 o[kPairs], dq[kPairs], acc1[kPairs], acc2[kPairs];
+    ld2<F>(o, a.v, b2, a.n);
+    if (a.dotcol >= 0) ld2<F>(dq, a.Q + (int64_t)a.dotcol * a.ldq, b2, a.n);
+    zero2(acc1);
+    zero2(acc2);
+    if (a.dcgs2_p >= 0) {
+      // Alg. 6: q'_p = q_p - Q_{:,0:p-1} s, then v - Q_{:,0:p-1} c - q'_p c_p
+      const int p = a.dcgs2_p;
+      double2 qp[kPairs];
+      ld2<F>(qp, a.Q + (int64_t)p * a.ldq, b2, a.n);
+      combine_cols<F>(a.Q, a.ldq, b2, a.n, 0, p, s_c1, a.reorth ? s_s : nullptr, acc1, acc2);
+      if (a.reorth) {
+#pragma unroll
+        for (int i = 0; i < kPairs; ++i) {
+          qp[i].x -= acc2[i].x;
+          qp[i].y -= acc2[i].y;
+        }
+        st2<F>(qp, a.Qw + (int64_t)p * a.ldq, b2, a.n);
+      }
+      const double cp = s_c1[p];
+#pragma unroll
+      for (int i = 0; i < kPairs; ++i) {
+        o[i].x = (o[i].x - acc1[i].x) - qp[i].x * cp;
+        o[i].y = (o[i].y - acc1[i].y) - qp[i].y * cp;
+      }
+    } else {
+      combine_cols<F>(a.Q, a.ldq, b2, a.n, a.j0, a.j0 + a.nc, s_c1, c2, acc1, acc2);
+#pragma unroll
+      for (int i = 0; i < kPairs; ++i) {
+        o[i].x = (o[i].x - acc1[i].x) - acc2[i].x;
+        o[i].y = (o[i].y - acc1[i].y) - acc2[i].y;
+      }
+    }
+    if (a.out) st2<F>(o, a.out, b2, a.n);
+    if (a.dotcol >= 0) {
+      const double p = wave_sum(dot2(dq, o));
+      if (lane == 0) acc[0] += p;
+    }
+    if (a.nrm) {
+      const double p = wave_sum(dot2(o, o));
+      if (lane == 0) acc[inorm] += p;
+    }
+  });
+}
+
+// ---------------------------------------------------------------------------
+// CGS-2 second pass (Alg. 5): y = v - Q s in registers, acc_w[j] += q_j^T y.
+// One row per thread (tiles of kWG rows), the row's k values held in registers.
+// ---------------------------------------------------------------------------
+
+template <int KMAX>
+__device__ inline void cgs2b_body(const Cgs2bArgs& a, const double* s_s, int64_t t0, int64_t ts,
+                                  double* acc) {
+  const int lane = threadIdx.x & 63;
+  const int64_t ntiles = (a.n + kWG - 1) / kWG;
+  for (int64_t tile = t0; tile < ntiles; tile += ts) {
+    const int64_t row = tile * kWG + threadIdx.x;
+    const bool valid = row < a.n;
+    double q[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j)
+      q[j] = (j < a.k && valid) ? a.Q[(int64_t)j * a.ldq + row] : 0.0;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) s = fma(q[j], s_s[j], s);
+    const double y = (valid ? a.v[row] : 0.0) - s;
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) q[j] *= y;
+    const double r = multi_reduce<KMAX>(q);
+    if (lane < KMAX) acc[lane] += r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// QRDelete (Alg. 2): Givens rotations from R, then one sweep over Q
+// ---------------------------------------------------------------------------
+
+// H = R_{:,1:k-1}; rotation j zeroes H_{j+1,j}; R <- the (k-1)x(k-1) triangle.
+// Any block size; every thread must call (barriers inside).  H: k*k doubles
+// of LDS.
+__device__ inline void givens_body(const Small& sm, int k, double* H) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int cap = sm.cap;
+  const int nc = k - 1;
+  for (int idx = tid; idx < k * nc; idx += nthr) {
+    const int i = idx % k, j = idx / k;
+    H[i + j * k] = sm.R[i + (size_t)(j + 1) * cap];
+  }
+  __syncthreads();
+  for (int j = 0; j < nc; ++j) {
+    const double x = H[j + j * k], y = H[(j + 1) + j * k];
+    const double rho = hypot(x, y);
+    const double c = rho > 0.0 ? x / rho : 1.0;
+    const double s = rho > 0.0 ? y / rho : 0.0;
+    __syncthreads();
+    for (int col = j + tid; col < nc; col += nthr) {
+      const double hj = H[j + col * k], hj1 = H[(j + 1) + col * k];
+      H[j + col * k] = c * hj + s * hj1;
+      H[(j + 1) + col * k] = -s * hj + c * hj1;
+    }
+    if (tid == 0) {
+      sm.givens[j] = c;
+      sm.givens[cap + j] = s;
+    }
+    __syncthreads();
+    if (tid == 0) H[(j + 1) + j * k] = 0.0;
+    __syncthreads();
+  }
+  for (int idx = tid; idx < k * k; idx += nthr) {
+    const int i = idx % k, j = idx / k;
+    sm.R[i + (size_t)j * cap] = (i < nc && j < nc && i <= j) ? H[i + j * k] : 0.0;
+  }
+}
+
+__device__ inline void givens_coefs(const RotArgs& a, int cap, double* s_c, double* s_s, int kmax) {
+  for (int j = threadIdx.x; j < kmax; j += blockDim.x) {
+    s_c[j] = (j < a.k - 1) ? a.givens[j] : 1.0;
+    s_s[j] = (j < a.k - 1) ? a.givens[cap + j] : 0.0;
+  }
+}
+
+// Per row: x <- q_0; for j < k-1: (q_j, x) <- (c x + s q_{j+1}, -s x + c q_{j+1}).
+// The k values of the row are loaded first (registers), so the loads do not
+// wait on the stores.
+template <int KMAX>
+__device__ __forceinline__ void rotate_row(double (&q)[KMAX], const RotArgs& a, int64_t row,
+                                           bool valid, const double* s_c, const double* s_s) {
+  const int kk = a.k - 1;
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j)
+    q[j] = (j < a.k && valid) ? a.Q[(int64_t)j * a.ldq + row] : 0.0;
+  double x = q[0];
+#pragma unroll
+  for (int j = 0; j < KMAX - 1; ++j) {
+    if (j < kk) {
+      const double y = q[j + 1];
+      const double c = s_c[j], s = s_s[j];
+      q[j] = c * x + s * y;
+      x = -s * x + c * y;
+    }
+  }
+  if (valid) {
+#pragma unroll
+    for (int j = 0; j < KMAX - 1; ++j)
+      if (j < kk) a.Q[(int64_t)j * a.ldq + row] = q[j];
+  }
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j)
+    if (j >= kk) q[j] = 0.0;
+}
+
+template <int KMAX>
+__device__ inline void rotate_body(const RotArgs& a, const double* s_c, const double* s_s,
+                                   int64_t t0, int64_t ts) {
+  const int64_t ntiles = (a.n + kWG - 1) / kWG;
+  for (int64_t tile = t0; tile < ntiles; tile += ts) {
+    const int64_t row = tile * kWG + threadIdx.x;
+    double q[KMAX];
+    rotate_row<KMAX>(q, a, row, row < a.n, s_c, s_s);
+  }
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <int KMAX>
+struct GramShape {
+  static_assert(KMAX % 16 == 0, "Gram blocks are 16 columns wide");
+  static constexpr int KP = KMAX + 1;            // LDS row stride (doubles)
+  static constexpr int NB = KMAX / 16;           // 16-column blocks
+  static constexpr int NBP = NB * (NB + 1) / 2;  // lower block pairs
+  static constexpr int NP = KMAX * (KMAX - 1) / 2;
+  static constexpr int STAGE = kWaves * 64 * KP; // staging doubles per workgroup
+};
+
+// ICWY after QRDelete (Sec. 3.2): rotate, then accumulate the strict lower
+// Gram matrix of the k-1 rotated columns, T_ab = q_a^T q_b (b < a).  The Gram
+// over rows is a dense contraction, done on the matrix cores: each wave stages
+// its 64 rotated rows in LDS (row stride KMAX + 1 doubles) and, 4 rows at a
+// time, issues v_mfma_f64_16x16x4 on every lower pair of 16-column blocks.
+// Operand layout of that instruction: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; lane l, register r of the result holds D[l / 16 + 4 r]
+// [l % 16].  Accumulators stay in registers across all tiles of the call.
+template <int KMAX>
+__device__ inline void rotate_gram_body(const RotArgs& a, const double* s_c, const double* s_s,
+                                        int64_t t0, int64_t ts, double* stage_all,
+                                        v4d (&acc)[GramShape<KMAX>::NBP]) {
+  using S = GramShape<KMAX>;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  double* stage = stage_all + w * 64 * S::KP;
+#pragma unroll
+  for (int p = 0; p < S::NBP; ++p) acc[p] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int64_t ntiles = (a.n + kWG - 1) / kWG;
+  for (int64_t tile = t0; tile < ntiles; tile += ts) {
+    const int64_t row = tile * kWG + threadIdx.x;
+    double q[KMAX];
+    rotate_row<KMAX>(q, a, row, row < a.n, s_c, s_s);
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) stage[lane * S::KP + j] = q[j];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 4
+    for (int r0 = 0; r0 < 64; r0 += 4) {
+      double v[S::NB];
+#pragma unroll
+      for (int b = 0; b < S::NB; ++b) v[b] = stage[(r0 + lk) * S::KP + b * 16 + li];
+      int p = 0;
+#pragma unroll
+      for (int bi = 0; bi < S::NB; ++bi)
+#pragma unroll
+        for (int bj = 0; bj <= bi; ++bj, ++p)
+          acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[bi], v[bj], acc[p], 0, 0, 0);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// Write this wave's Gram accumulators as pair sums accw[a(a-1)/2 + b], b < a.
+template <int KMAX>
+__device__ inline void gram_store(const v4d (&acc)[GramShape<KMAX>::NBP], double* accw) {
+  using S = GramShape<KMAX>;
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  int p = 0;
+#pragma unroll
+  for (int bi = 0; bi < S::NB; ++bi)
+#pragma unroll
+    for (int bj = 0; bj <= bi; ++bj, ++p)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ia = bi * 16 + lk + 4 * r, ib = bj * 16 + li;
+        if (ia > ib) accw[ia * (ia - 1) / 2 + ib] = acc[p][r];
+      }
+}
+
+// ---------------------------------------------------------------------------
+// elementwise passes
+// ---------------------------------------------------------------------------
+
+// out = in / d over pairs p = t0 * kWG + tid, stride ts * kWG (and the odd tail).
+__device__ inline void scale_body(const double* in, double* out, int64_t n, double d,
+                                  int64_t t0, int64_t ts) {
+  const int64_t npair = n / 2;
+  const double2* in2 = reinterpret_cast<const double2*>(in);
+  double2* out2 = reinterpret_cast<double2*>(out);
+  for (int64_t r = t0 * kWG + threadIdx.x; r < npair; r += ts * kWG) {
+    const double2 v = in2[r];
+    out2[r] = make_double2(v.x / d, v.y / d);
+  }
+  if (t0 == 0 && threadIdx.x == 0 && (n & 1)) out[n - 1] = in[n - 1] / d;
+}
+
+// i >= 1 (Alg. 1): f = g - x; Delta f = f - f_prev -> W; Delta g = g - g_prev
+// -> ring slot; f_prev <- f; g_prev <- g; acc_w[0] += ||f||^2.
+// i == 0: f_prev = g - x, g_prev = g, x_next = g; acc_w[0..1] += ||f||^2.
+__device__ inline void history_body(const HistArgs& a, int64_t t0, int64_t ts, double* acc) {
+  const int lane = threadIdx.x & 63;
+  for_tiles(a.n, t0, ts, [&](int64_t b2, auto full) {
+    constexpr bool F = decltype(full)::value;
+    double2 xv[kPairs], gv[kPairs], f[kPairs];
+    ld2<F>(xv, a.x, b2, a.n);
+    ld2<F>(gv, a.g, b2, a.n);
+    if (a.first) {
+#pragma unroll
+      for (int i = 0; i < kPairs; ++i) f[i] = make_double2(gv[i].x - xv[i].x, gv[i].y - xv[i].y);
+      st2<F>(f, a.f_prev, b2, a.n);
+      st2<F>(gv, a.g_prev, b2, a.n);
+      st2<F>(gv, a.x_next, b2, a.n);
+    } else {
+      double2 fp[kPairs], gp[kPairs];
+      ld2<F>(fp, a.f_prev, b2, a.n);
+      ld2<F>(gp, a.g_prev, b2, a.n);
+#pragma unroll
+      for (int i = 0; i < kPairs; ++i) {
+        f[i] = make_double2(gv[i].x - xv[i].x, gv[i].y - xv[i].y);
+        fp[i] = make_double2(f[i].x - fp[i].x, f[i].y - fp[i].y);
+        gp[i] = make_double2(gv[i].x - gp[i].x, gv[i].y - gp[i].y);
+      }
+      st2<F>(fp, a.W, b2, a.n);
+      st2<F>(gp, a.dg, b2, a.n);
+      st2<F>(f, a.f_prev, b2, a.n);
+      st2<F>(gv, a.g_prev, b2, a.n);
+    }
+    const double p = wave_sum(dot2(f, f));
+    if (lane == 0) {
+      acc[0] += p;
+      acc[1] += p;  // first step: x_1 - x_0 = f_0
+    }
+  });
+}
+
+// Alg. 1: x_{i+1} = g_i - sum_j gamma_j Delta g_{i-m_i+j}; acc_w[0] += ||x_{i+1}-x_i||^2.
+__device__ inline void xupdate_coefs(const XupdArgs& a, double* s_g, int* s_slot) {
+  for (int j = threadIdx.x; j < a.mi; j += blockDim.x) {
+    s_g[j] = a.gamma[j];
+    s_slot[j] = (a.slot0 + j) % a.m;
+  }
+}
+
+__device__ inline void xupdate_body(const XupdArgs& a, const double* s_g, const int* s_slot,
+                                    int64_t t0, int64_t ts, double* acc) {
+  const int lane = threadIdx.x & 63;
+  for_tiles(a.n, t0, ts, [&](int64_t b2, auto full) {
+    constexpr bool F = decltype(full)::value;
+    double2 gv[kPairs], xv[kPairs], sum[kPairs];
+    ld2<F>(gv, a.g, b2, a.n);
+    ld2<F>(xv, a.x, b2, a.n);
+    zero2(sum);
+    for (int g0 = 0; g0 < a.mi; g0 += kGroup) {
+      double2 d[kGroup][kPairs];
+#pragma unroll
+      for (int c = 0; c < kGroup; ++c) {
+        if (g0 + c < a.mi)
+          ld2<F>(d[c], a.ring + (int64_t)s_slot[g0 + c] * a.ldq, b2, a.n);
+        else
+          zero2(d[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < kGroup; ++c)
+        if (g0 + c < a.mi) axpy2(sum, d[c], s_g[g0 + c]);
+    }
+    double d2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < kPairs; ++i) {
+      const double2 xn = make_double2(gv[i].x - sum[i].x, gv[i].y - sum[i].y);
+      const double dx = xn.x - xv[i].x, dy = xn.y - xv[i].y;
+      d2 = fma(dx, dx, d2);
+      d2 = fma(dy, dy, d2);
+      gv[i] = xn;
+    }
+    st2<F>(gv, a.x_next, b2, a.n);
+    const double p = wave_sum(d2);
+    if (lane == 0) acc[0] += p;
+  });
+}
+
+}  // namespace aa
