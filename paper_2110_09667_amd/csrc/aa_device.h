@@ -107,6 +107,9 @@ __device__ __forceinline__ void axpy2(double2 (&acc)[kPairs], const double2 (&q)
   }
 }
 
-constexpr int kGroup = 4;  // Q columns loaded together (kGroup * kPairs loads in flight)
+#ifndef AA_GROUP
+#define AA_GROUP 4
+#endif
+constexpr int kGroup = AA_GROUP;  // Q columns loaded together (kGroup * kPairs loads in flight)
 
 }  // namespace aa

@@ -11,7 +11,10 @@ namespace aa {
 
 constexpr int kWG = 256;             // threads per workgroup (4 wave64s)
 constexpr int kWaves = kWG / 64;
-constexpr int kPairs = 4;            // row pairs (16-byte loads) per lane per tile
+#ifndef AA_PAIRS
+#define AA_PAIRS 2
+#endif
+constexpr int kPairs = AA_PAIRS;     // row pairs (16-byte loads) per lane per tile
 constexpr int kTile = kWG * 2 * kPairs;  // rows per tile in streaming passes
 constexpr int kMaxCols = AA_MAX_COLS;
 constexpr int kMaxRed = 2 * kMaxCols + 4;  // reductions of one streaming pass
@@ -119,6 +122,43 @@ struct XupdArgs {
   const double* g; const double* x; double* x_next; int64_t n;
   const double* gamma;
 };
+
+// ---- batched / fused workgroup-level step (aa_batch.hip) ---------------------
+
+// One AA instance processed by one workgroup.  Pointers into the workspace
+// except x, f (caller's) and, for dim == 0, g (the caller's G(x)).
+struct BInst {
+  int64_t n, ld;          // length, leading dimension of Q / ring (even)
+  int m;                  // window
+  int dim;                // model map on an s^dim grid (1..3); 0: caller's g
+  int64_t s;
+  double h, omega, c;
+  const double* f;        // model right-hand side
+  double* x;              // iterate (updated in place)
+  double* g;              // G(x) buffer (dim > 0) or the caller's G(x)
+  double* f_prev; double* g_prev; double* W; double* Q; double* ring;
+  Small sm;               // R, T, coefficients, gamma, Givens, scalars, status
+};
+
+// Per-instance iteration state, updated on the device.
+struct BState {
+  int64_t iter;           // index i of the next iteration
+  int64_t conv_iter;      // iteration at which the instance stopped (-1: running)
+  int k, m_i, active, status;
+  double res_norm, res0_norm;
+};
+
+struct BatchArgs {
+  BInst* inst; BState* state; const int* order; int count;
+  unsigned* counter;      // work counter, reset before every launch
+  int variant; unsigned flags;
+  double tol; int64_t max_iter;
+  // single-instance override (count == 1, fused aa_step): x, G(x), x_next
+  const double* ox; const double* og; double* oxn;
+};
+
+hipError_t launch_batch(const BatchArgs&, int grid, int kbucket, bool gram, hipStream_t);
+hipError_t launch_batch_reset(unsigned* counter, hipStream_t);
 
 // launchers (aa_kernels.hip)
 hipError_t launch_dots(const DotsArgs&, const Small&, const Tail&, int grid, hipStream_t);

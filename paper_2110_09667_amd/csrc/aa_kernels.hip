@@ -82,12 +82,11 @@ __global__ __launch_bounds__(64) void k_givens(Small sm, int k) {
   givens_body(sm, k, H);
 }
 
-template <int KMAX>
 __global__ __launch_bounds__(kWG) void k_rotate(RotArgs a, Small sm) {
-  __shared__ double s_c[KMAX], s_s[KMAX];
-  givens_coefs(a, sm.cap, s_c, s_s, KMAX);
+  __shared__ double s_c[kMaxCols], s_s[kMaxCols];
+  givens_coefs(a, sm.cap, s_c, s_s, kMaxCols);
   __syncthreads();
-  rotate_body<KMAX>(a, s_c, s_s, blockIdx.x, gridDim.x);
+  rotate_body(a, s_c, s_s, blockIdx.x, gridDim.x);
 }
 
 template <int KMAX>
@@ -214,16 +213,7 @@ hipError_t launch_rotate(const RotArgs& a, const Small& sm, const Tail& t, int g
       return hipErrorInvalidValue;  // the ICWY window is limited to 64 columns
     return launch_finalize(sm, t, (a.k - 1) * (a.k - 2) / 2, grid, st);
   }
-  if (a.k <= 8)
-    hipLaunchKernelGGL(k_rotate<8>, dim3(grid), dim3(kWG), 0, st, a, sm);
-  else if (a.k <= 16)
-    hipLaunchKernelGGL(k_rotate<16>, dim3(grid), dim3(kWG), 0, st, a, sm);
-  else if (a.k <= 32)
-    hipLaunchKernelGGL(k_rotate<32>, dim3(grid), dim3(kWG), 0, st, a, sm);
-  else if (a.k <= 64)
-    hipLaunchKernelGGL(k_rotate<64>, dim3(grid), dim3(kWG), 0, st, a, sm);
-  else
-    hipLaunchKernelGGL(k_rotate<65>, dim3(grid), dim3(kWG), 0, st, a, sm);
+  hipLaunchKernelGGL(k_rotate, dim3(grid), dim3(kWG), 0, st, a, sm);
   return hipGetLastError();
 }
 

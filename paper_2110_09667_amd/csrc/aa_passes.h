@@ -318,6 +318,31 @@ __device__ inline void cgs2b_body(const Cgs2bArgs& a, const double* s_s, int64_t
   }
 }
 
+// The same pass without a k-wide register array (workgroup-level step): per
+// 256-row tile, one sweep forms y = v - Q s, a second sweep over the same tile
+// (cache-resident, just read) forms Q^T y in groups of kGroup columns.
+__device__ inline void cgs2b_stream_body(const Cgs2bArgs& a, const double* s_s, int64_t t0,
+                                         int64_t ts, double* acc) {
+  const int lane = threadIdx.x & 63;
+  const int64_t ntiles = (a.n + kWG - 1) / kWG;
+  for (int64_t tile = t0; tile < ntiles; tile += ts) {
+    const int64_t row = tile * kWG + threadIdx.x;
+    const bool valid = row < a.n;
+    const double* qrow = a.Q + row;
+    double s = 0.0;
+    for (int j = 0; j < a.k; ++j) s = fma(valid ? qrow[(int64_t)j * a.ldq] : 0.0, s_s[j], s);
+    const double y = (valid ? a.v[row] : 0.0) - s;
+    for (int j0 = 0; j0 < a.k; j0 += kGroup) {
+      double v[kGroup];
+#pragma unroll
+      for (int c = 0; c < kGroup; ++c)
+        v[c] = (valid && j0 + c < a.k) ? qrow[(int64_t)(j0 + c) * a.ldq] * y : 0.0;
+      const double r = multi_reduce<kGroup>(v);
+      if (lane < kGroup && j0 + lane < a.k) acc[j0 + lane] += r;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // QRDelete (Alg. 2): Givens rotations from R, then one sweep over Q
 // ---------------------------------------------------------------------------
@@ -366,44 +391,55 @@ __device__ inline void givens_coefs(const RotArgs& a, int cap, double* s_c, doub
   }
 }
 
-// Per row: x <- q_0; for j < k-1: (q_j, x) <- (c x + s q_{j+1}, -s x + c q_{j+1}).
-// The k values of the row are loaded first (registers), so the loads do not
-// wait on the stores.
-template <int KMAX>
-__device__ __forceinline__ void rotate_row(double (&q)[KMAX], const RotArgs& a, int64_t row,
-                                           bool valid, const double* s_c, const double* s_s) {
+// Per row: x <- q_0; for j < k-1: (q_j, x) <- (c_j x + s_j q_{j+1},
+// -s_j x + c_j q_{j+1}) -- rotation j of QRDelete applied to columns j, j+1
+// of Q, in the order the rotations were generated.  The sweep streams the
+// columns in chunks of kRotCh with the next chunk's loads issued before the
+// current chunk's stores (registers hold two chunks, not the whole row).
+// Each rotated value is also passed to emit(j, value) (the ICWY Gram stages it).
+constexpr int kRotCh = 8;
+
+template <class Emit>
+__device__ __forceinline__ void rotate_row(const RotArgs& a, int64_t row, bool valid,
+                                           const double* s_c, const double* s_s, Emit&& emit) {
   const int kk = a.k - 1;
+  const double* qrow = a.Q + row;
+  double* qw = a.Q + row;
+  double x = valid ? qrow[0] : 0.0;
+  double nxt[kRotCh];
 #pragma unroll
-  for (int j = 0; j < KMAX; ++j)
-    q[j] = (j < a.k && valid) ? a.Q[(int64_t)j * a.ldq + row] : 0.0;
-  double x = q[0];
+  for (int c = 0; c < kRotCh; ++c)
+    nxt[c] = (valid && 1 + c < a.k) ? qrow[(int64_t)(1 + c) * a.ldq] : 0.0;
+  for (int j0 = 0; j0 < kk; j0 += kRotCh) {
+    double cur[kRotCh];
 #pragma unroll
-  for (int j = 0; j < KMAX - 1; ++j) {
-    if (j < kk) {
-      const double y = q[j + 1];
-      const double c = s_c[j], s = s_s[j];
-      q[j] = c * x + s * y;
-      x = -s * x + c * y;
+    for (int c = 0; c < kRotCh; ++c) cur[c] = nxt[c];
+#pragma unroll
+    for (int c = 0; c < kRotCh; ++c) {
+      const int jn = j0 + kRotCh + 1 + c;
+      nxt[c] = (valid && jn < a.k) ? qrow[(int64_t)jn * a.ldq] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < kRotCh; ++c) {
+      const int j = j0 + c;
+      if (j < kk) {
+        const double y = cur[c];
+        const double cj = s_c[j], sj = s_s[j];
+        const double qn = cj * x + sj * y;
+        x = -sj * x + cj * y;
+        if (valid) qw[(int64_t)j * a.ldq] = qn;
+        emit(j, valid ? qn : 0.0);
+      }
     }
   }
-  if (valid) {
-#pragma unroll
-    for (int j = 0; j < KMAX - 1; ++j)
-      if (j < kk) a.Q[(int64_t)j * a.ldq + row] = q[j];
-  }
-#pragma unroll
-  for (int j = 0; j < KMAX; ++j)
-    if (j >= kk) q[j] = 0.0;
 }
 
-template <int KMAX>
 __device__ inline void rotate_body(const RotArgs& a, const double* s_c, const double* s_s,
                                    int64_t t0, int64_t ts) {
   const int64_t ntiles = (a.n + kWG - 1) / kWG;
   for (int64_t tile = t0; tile < ntiles; tile += ts) {
     const int64_t row = tile * kWG + threadIdx.x;
-    double q[KMAX];
-    rotate_row<KMAX>(q, a, row, row < a.n, s_c, s_s);
+    rotate_row(a, row, row < a.n, s_c, s_s, [](int, double) {});
   }
 }
 
@@ -438,12 +474,12 @@ __device__ inline void rotate_gram_body(const RotArgs& a, const double* s_c, con
 #pragma unroll
   for (int p = 0; p < S::NBP; ++p) acc[p] = v4d{0.0, 0.0, 0.0, 0.0};
   const int64_t ntiles = (a.n + kWG - 1) / kWG;
+  const int kk = a.k - 1;
   for (int64_t tile = t0; tile < ntiles; tile += ts) {
     const int64_t row = tile * kWG + threadIdx.x;
-    double q[KMAX];
-    rotate_row<KMAX>(q, a, row, row < a.n, s_c, s_s);
-#pragma unroll
-    for (int j = 0; j < KMAX; ++j) stage[lane * S::KP + j] = q[j];
+    double* srow = stage + lane * S::KP;
+    rotate_row(a, row, row < a.n, s_c, s_s, [&](int j, double v) { srow[j] = v; });
+    for (int j = kk; j < KMAX; ++j) srow[j] = 0.0;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -486,6 +522,31 @@ __device__ inline void gram_store(const v4d (&acc)[GramShape<KMAX>::NBP], double
 // ---------------------------------------------------------------------------
 // elementwise passes
 // ---------------------------------------------------------------------------
+
+// G(u)_p = u_p - omega ((A u)_p + c u_p^3 - f_p), A the (2 dim + 1)-point
+// Dirichlet Laplacian on an s^dim grid (x fastest) scaled by ih2 = 1/h^2.
+__device__ __forceinline__ double stencil_point(const double* __restrict__ u,
+                                                const double* __restrict__ f, int dim,
+                                                int64_t s, double ih2, double omega, double c,
+                                                int64_t p) {
+  const int64_t ix = p % s;
+  const double up = u[p];
+  double nb = 0.0;
+  if (ix > 0) nb += u[p - 1];
+  if (ix < s - 1) nb += u[p + 1];
+  if (dim >= 2) {
+    const int64_t iy = (p / s) % s;
+    if (iy > 0) nb += u[p - s];
+    if (iy < s - 1) nb += u[p + s];
+  }
+  if (dim >= 3) {
+    const int64_t s2 = s * s, iz = p / s2;
+    if (iz > 0) nb += u[p - s2];
+    if (iz < s - 1) nb += u[p + s2];
+  }
+  const double au = (2.0 * dim * up - nb) * ih2;
+  return up - omega * (au + c * up * up * up - f[p]);
+}
 
 // out = in / d over pairs p = t0 * kWG + tid, stride ts * kWG (and the odd tail).
 __device__ inline void scale_body(const double* in, double* out, int64_t n, double d,

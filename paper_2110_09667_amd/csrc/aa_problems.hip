@@ -5,7 +5,7 @@
 // 3D nonlinear and 2D batched workloads all use it (dim = 1, 3, 2).
 #include <math.h>
 
-#include "aa_internal.h"
+#include "aa_passes.h"
 
 namespace aa {
 
@@ -13,27 +13,9 @@ __global__ __launch_bounds__(256) void k_stencil(int dim, int64_t s, double ih2,
                                                  double c, const double* __restrict__ f,
                                                  const double* __restrict__ u,
                                                  double* __restrict__ out, int64_t n) {
-  const int64_t s2 = s * s;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t ix = p % s;
-    const double up = u[p];
-    double nb = 0.0;
-    if (ix > 0) nb += u[p - 1];
-    if (ix < s - 1) nb += u[p + 1];
-    if (dim >= 2) {
-      const int64_t iy = (p / s) % s;
-      if (iy > 0) nb += u[p - s];
-      if (iy < s - 1) nb += u[p + s];
-    }
-    if (dim >= 3) {
-      const int64_t iz = p / s2;
-      if (iz > 0) nb += u[p - s2];
-      if (iz < s - 1) nb += u[p + s2];
-    }
-    const double au = (2.0 * dim * up - nb) * ih2;
-    out[p] = up - omega * (au + c * up * up * up - f[p]);
-  }
+       p += (int64_t)gridDim.x * blockDim.x)
+    out[p] = stencil_point(u, f, dim, s, ih2, omega, c, p);
 }
 
 hipError_t launch_stencil(int dim, int64_t s, double h, double omega, double c,
