@@ -155,7 +155,8 @@ typedef enum {
   AA_K_SCALE = 5,   /* q_k = w / R_kk                                     */
   AA_K_HISTORY = 6, /* f_i, Delta f, Delta g                              */
   AA_K_XUPDATE = 7, /* x_{i+1} = G(x_i) - sum gamma_j Delta g_j           */
-  AA_K_COUNT = 8
+  AA_K_FUSED = 8,   /* whole iteration in one workgroup (small n)         */
+  AA_K_COUNT = 9
 } aa_kernel_kind;
 
 /* Enable (1) or disable (0) per-launch timing: every kernel the context
@@ -176,6 +177,67 @@ aa_status aa_profile_reset(aa_ctx *ctx);
  * Gram pass (defaults 1024 and 256; each in [1, 4096], and the Gram bound
  * times (m-1)(m-2)/2 may not exceed 134 * 4096). */
 aa_status aa_set_grid(aa_ctx *ctx, int stream_max, int gram_max);
+
+/* Largest n for which aa_step runs the whole iteration in one workgroup (one
+ * launch instead of one per pass; default 16384, 0 disables, m <= 64). */
+aa_status aa_set_fused_threshold(aa_ctx *ctx, int64_t n_max);
+
+/* ---------------- batched AA: many independent instances ------------------ */
+
+/* Thousands of independent AA instances of uneven length n and window m
+ * advance one iteration each per persistent launch: every workgroup pulls
+ * instances from a work counter (largest n*m first) and runs the whole
+ * iteration of Alg. 1 for that instance -- the model map G, history, QRDelete,
+ * QRAdd by the chosen variant, R gamma = Q^T f_i, the x update -- so every
+ * Sync of Sec. 3 becomes a workgroup barrier.  An instance stops (and is
+ * skipped from then on) when ||f_i|| <= tol ||f_0|| at the start of iteration
+ * i, when i reaches max_iter, or on breakdown. */
+typedef struct aa_batch aa_batch;
+
+typedef struct {
+  int64_t n;          /* vector length; n = s^dim                             */
+  int m;              /* window, 1 <= m <= 64                                 */
+  int dim;            /* model map G(u) = u - omega (A u + c u^3 - f) on an
+                         s^dim Dirichlet grid (dim 1, 2 or 3)                 */
+  int64_t s;          /* grid points per side                                 */
+  double h, omega, c; /* spacing, relaxation weight, cubic coefficient        */
+  const double *d_f;  /* right-hand side f, n doubles (device, caller-owned)  */
+  double *d_x;        /* iterate: x_0 on entry; the current x_i afterwards
+                         (device, caller-owned, 16-byte aligned)              */
+} aa_batch_instance;
+
+typedef struct {
+  int64_t iter;       /* index i of the next iteration                        */
+  int64_t stop_iter;  /* iteration i at which the instance stopped, -1 if not */
+  int k, m_i, active, status;
+  double res_norm;    /* ||f_i||_2 at the last history formation              */
+  double res0_norm;   /* ||f_0||_2                                            */
+} aa_batch_state;
+
+aa_status aa_batch_workspace_size(int count, const aa_batch_instance *h_inst,
+                                  int variant, unsigned flags, size_t *bytes);
+
+/* h_inst: count descriptors (host; copied).  The workspace (device,
+ * 256-byte aligned, caller-owned) holds every instance's Q, history, R, T and
+ * the schedule.  stream: a hipStream_t; a non-NULL stream lets aa_batch_run
+ * replay a captured HIP graph. */
+aa_status aa_batch_init(aa_batch **b, int count, const aa_batch_instance *h_inst,
+                        int variant, unsigned flags, double tol, int64_t max_iter,
+                        void *d_workspace, size_t bytes, void *stream);
+
+/* Enqueue `iters` batched iterations (asynchronous). */
+aa_status aa_batch_run(aa_batch *b, int iters);
+
+/* Copy the per-instance states (h_states: count entries, may be NULL) and the
+ * number of active instances (may be NULL).  Waits for the stream. */
+aa_status aa_batch_read(aa_batch *b, aa_batch_state *h_states, int *h_active);
+
+/* Schedule knobs (the autotuner's search space): persistent workgroups
+ * (0 = 2 per compute unit), instance order (0 = largest n*m first,
+ * 1 = as given), graph replay on/off. */
+aa_status aa_batch_set_schedule(aa_batch *b, int grid, int order, int use_graph);
+
+aa_status aa_batch_destroy(aa_batch *b);
 
 /* ---------------- model fixed-point maps and seeded inputs --------------- */
 

@@ -28,10 +28,13 @@ SYMBOLS = [
     "aa_qr_add", "aa_qr_delete", "aa_qr_solve", "aa_get_qr", "aa_qr_basis",
     "aa_qr_load", "aa_reset", "aa_destroy", "aa_sync_counts", "aa_problem_apply",
     "aa_fill_uniform", "aa_fill_normal", "aa_version", "aa_profile_enable",
-    "aa_profile_read", "aa_profile_reset", "aa_set_grid",
+    "aa_profile_read", "aa_profile_reset", "aa_set_grid", "aa_set_fused_threshold",
+    "aa_batch_workspace_size", "aa_batch_init", "aa_batch_run", "aa_batch_read",
+    "aa_batch_set_schedule", "aa_batch_destroy",
 ]
 
-KERNEL_KINDS = ["dots", "update", "cgs2b", "givens", "rotate", "scale", "history", "xupdate"]
+KERNEL_KINDS = ["dots", "update", "cgs2b", "givens", "rotate", "scale", "history", "xupdate",
+                "fused"]
 
 
 class AAError(RuntimeError):
@@ -44,6 +47,18 @@ class Info(C.Structure):
     _fields_ = [("iter", C.c_int64), ("m_i", C.c_int), ("k", C.c_int),
                 ("res_norm", C.c_double), ("res0_norm", C.c_double),
                 ("step_norm", C.c_double), ("status", C.c_int)]
+
+
+class BatchInstance(C.Structure):
+    _fields_ = [("n", C.c_int64), ("m", C.c_int), ("dim", C.c_int), ("s", C.c_int64),
+                ("h", C.c_double), ("omega", C.c_double), ("c", C.c_double),
+                ("d_f", C.c_void_p), ("d_x", C.c_void_p)]
+
+
+class BatchState(C.Structure):
+    _fields_ = [("iter", C.c_int64), ("stop_iter", C.c_int64), ("k", C.c_int),
+                ("m_i", C.c_int), ("active", C.c_int), ("status", C.c_int),
+                ("res_norm", C.c_double), ("res0_norm", C.c_double)]
 
 
 _lib = None
@@ -81,6 +96,14 @@ def lib():
         "aa_profile_read": [P, I, C.POINTER(D), C.POINTER(I64), C.POINTER(D)],
         "aa_profile_reset": [P],
         "aa_set_grid": [P, I, I],
+        "aa_set_fused_threshold": [P, I64],
+        "aa_batch_workspace_size": [I, C.POINTER(BatchInstance), I, U, C.POINTER(C.c_size_t)],
+        "aa_batch_init": [C.POINTER(P), I, C.POINTER(BatchInstance), I, U, D, I64, P,
+                          C.c_size_t, P],
+        "aa_batch_run": [P, I],
+        "aa_batch_read": [P, C.POINTER(BatchState), C.POINTER(I)],
+        "aa_batch_set_schedule": [P, I, I, I],
+        "aa_batch_destroy": [P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -219,6 +242,47 @@ def aa_set_grid(ctx, stream_max: int, gram_max: int):
     _check(lib().aa_set_grid(ctx, stream_max, gram_max), "aa_set_grid")
 
 
+def aa_set_fused_threshold(ctx, n_max: int):
+    _check(lib().aa_set_fused_threshold(ctx, n_max), "aa_set_fused_threshold")
+
+
+def aa_batch_workspace_size(insts, variant: int, flags: int = 0) -> int:
+    arr = (BatchInstance * len(insts))(*insts)
+    b = C.c_size_t(0)
+    _check(lib().aa_batch_workspace_size(len(insts), arr, variant, flags, C.byref(b)),
+           "aa_batch_workspace_size")
+    return b.value
+
+
+def aa_batch_init(insts, variant, flags, tol, max_iter, workspace, stream=None):
+    arr = (BatchInstance * len(insts))(*insts)
+    b = C.c_void_p()
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(lib().aa_batch_init(C.byref(b), len(insts), arr, variant, flags, tol, max_iter,
+                               workspace.data_ptr(), nbytes, _stream(stream)), "aa_batch_init")
+    return b
+
+
+def aa_batch_run(b, iters: int):
+    _check(lib().aa_batch_run(b, iters), "aa_batch_run")
+
+
+def aa_batch_read(b, count: int):
+    states = (BatchState * count)()
+    active = C.c_int(0)
+    _check(lib().aa_batch_read(b, states, C.byref(active)), "aa_batch_read")
+    return list(states), active.value
+
+
+def aa_batch_set_schedule(b, grid: int = 0, order: int = 0, use_graph: bool = True):
+    _check(lib().aa_batch_set_schedule(b, grid, order, 1 if use_graph else 0),
+           "aa_batch_set_schedule")
+
+
+def aa_batch_destroy(b):
+    _check(lib().aa_batch_destroy(b), "aa_batch_destroy")
+
+
 def aa_version() -> str:
     return lib().aa_version().decode()
 
@@ -278,6 +342,9 @@ class AAContext:
     def set_grid(self, stream_max: int, gram_max: int):
         aa_set_grid(self.ctx, stream_max, gram_max)
 
+    def set_fused_threshold(self, n_max: int):
+        aa_set_fused_threshold(self.ctx, n_max)
+
     def sync_counts(self):
         return aa_sync_counts(self.ctx)
 
@@ -288,6 +355,50 @@ class AAContext:
         if getattr(self, "ctx", None) is not None:
             aa_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class AABatch:
+    """Owns the workspace of a batch of model-map instances (2D/3D stencils)."""
+
+    def __init__(self, problems, ms, variant="icwy", flags: int = 0, tol: float = 1e-8,
+                 max_iter: int = 5000, x0=None, stream=None, device="cuda"):
+        import torch
+        self.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        self.count = len(problems)
+        self.f = []
+        self.x = []
+        insts = []
+        for j, (p, m) in enumerate(zip(problems, ms)):
+            fj = p.f if hasattr(p.f, "data_ptr") else torch.from_numpy(p.f).to(device)
+            xj = torch.zeros(p.n, dtype=torch.float64, device=device) if x0 is None else \
+                x0[j].clone()
+            self.f.append(fj)
+            self.x.append(xj)
+            insts.append(BatchInstance(p.n, int(m), p.d, p.s, p.h, p.omega, p.c,
+                                       fj.data_ptr(), xj.data_ptr()))
+        nbytes = aa_batch_workspace_size(insts, self.variant, flags)
+        self.workspace = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=device)
+        self.b = aa_batch_init(insts, self.variant, flags, tol, max_iter, self.workspace, stream)
+
+    def run(self, iters: int):
+        aa_batch_run(self.b, iters)
+
+    def read(self):
+        return aa_batch_read(self.b, self.count)
+
+    def set_schedule(self, grid: int = 0, order: int = 0, use_graph: bool = True):
+        aa_batch_set_schedule(self.b, grid, order, use_graph)
+
+    def close(self):
+        if getattr(self, "b", None) is not None:
+            aa_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

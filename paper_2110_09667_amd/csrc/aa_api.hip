@@ -7,6 +7,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <limits.h>
 #include <new>
 #include <vector>
 
@@ -30,6 +31,10 @@ struct aa_ctx {
   int64_t iter = 0;
   int k = 0, m_i = 0;
   int64_t syncs_add = 0, syncs_del = 0, syncs_rhs = 0;
+  // fused single-workgroup step for small n (aa_batch.hip)
+  BInst* d_binst = nullptr;
+  BState* d_bstate = nullptr;
+  int64_t fused_max = 16384;
   // per-launch timing (aa_profile_enable)
   bool prof_on = false;
   std::vector<hipEvent_t> ev;   // pairs: 2 p (start), 2 p + 1 (stop)
@@ -61,7 +66,7 @@ int64_t leading_dim(int64_t n) {
 struct Layout {
   int64_t ldq;
   size_t off_Q, off_ring, off_W, off_fp, off_gp, off_R, off_T, off_c0, off_c1, off_gam,
-      off_giv, off_scal, off_status, off_part, total;
+      off_giv, off_scal, off_status, off_part, off_binst, off_bstate, total;
 };
 
 Layout make_layout(int64_t n, int m, unsigned flags) {
@@ -87,6 +92,8 @@ Layout make_layout(int64_t n, int m, unsigned flags) {
   L.off_status = o; o = align_up(o + sizeof(int));
   const size_t part = kPartials;
   L.off_part = o; o = align_up(o + sizeof(double) * part);
+  L.off_binst = o; o = align_up(o + sizeof(BInst));
+  L.off_bstate = o; o = align_up(o + sizeof(BState));
   L.total = o;
   return L;
 }
@@ -284,6 +291,77 @@ aa_status rhs_impl(aa_ctx* c, const double* f) {
   return hip_ok(e);
 }
 
+// Algorithmic vectors moved by QRAdd with k columns present (Algs. 3-6).
+double add_vectors(int variant, unsigned flags, int k) {
+  if (k == 0) return 3;
+  switch (variant) {
+    case AA_MGS: return 4.0 * k + 3;
+    case AA_CGS2: return 3.0 * k + 6;
+    case AA_ICWY: return 2.0 * k + 5;
+    default: {
+      const int m_i = k + 1;
+      const bool reorth = (flags & AA_DCGS2_GUARD_GE3) ? (m_i >= 3) : (m_i > 3);
+      return 2.0 * k + (reorth ? 6 : 5);
+    }
+  }
+}
+
+int64_t add_syncs(int variant, int k) {
+  if (k == 0) return 1;
+  switch (variant) {
+    case AA_MGS: return k + 1;
+    case AA_CGS2: return 3;
+    default: return 2;
+  }
+}
+
+// One iteration in a single workgroup (the batched step with one instance and
+// the host's counters); same sequence and arithmetic as the grid path.
+aa_status fused_step(aa_ctx* c, const double* x, const double* g, double* x_next) {
+  BatchArgs a{};
+  a.inst = c->d_binst;
+  a.state = c->d_bstate;
+  a.count = 1;
+  a.variant = c->variant;
+  a.flags = c->flags;
+  a.tol = 0.0;
+  a.max_iter = INT64_MAX;
+  a.ox = x; a.og = g; a.oxn = x_next;
+  a.ov_iter = c->iter;
+  a.ov_k = c->k;
+  const int kb = c->m <= 8 ? 8 : c->m <= 16 ? 16 : c->m <= 32 ? 32 : 64;
+  const bool gram = c->variant == AA_ICWY;
+  // model bytes and reduction counts of this iteration
+  double vecs = 5;
+  const int64_t i = c->iter;
+  int k = c->k;
+  if (i > 0) {
+    const int m_i = (int)(i < c->m ? i : c->m);
+    vecs = 8;
+    if (i > c->m) {
+      vecs += 2.0 * k - 1;
+      if (gram && k > 1) c->syncs_del += 1;
+      k -= 1;
+    }
+    vecs += add_vectors(c->variant, c->flags, k);
+    c->syncs_add += add_syncs(c->variant, k);
+    vecs += (k + 1) + (m_i + 3);
+    c->syncs_rhs += 1;
+  }
+  hipError_t e = timed(c, AA_K_FUSED, vecs,
+                       [&] { return launch_batch(a, 1, kb, gram, c->stream); });
+  if (e != hipSuccess) return AA_EHIP;
+  if (i == 0) {
+    c->iter = 1;
+    c->m_i = 0;
+  } else {
+    c->m_i = (int)(i < c->m ? i : c->m);
+    c->k = k + 1;
+    c->iter = i + 1;
+  }
+  return AA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -336,6 +414,25 @@ aa_status aa_init(aa_ctx** ctx, int64_t n, int m, int variant, unsigned flags,
     delete c;
     return AA_EHIP;
   }
+  if (!(flags & AA_QR_ONLY) && m <= 64) {
+    // descriptor of this context for the fused single-workgroup step
+    BInst I{};
+    I.n = n; I.ld = c->ldq; I.m = m; I.dim = 0;
+    I.f_prev = c->f_prev; I.g_prev = c->g_prev; I.W = c->W; I.Q = c->Q; I.ring = c->ring;
+    I.sm = c->sm;
+    BState st{};
+    st.conv_iter = -1;
+    st.active = 1;
+    c->d_binst = (BInst*)(base + L.off_binst);
+    c->d_bstate = (BState*)(base + L.off_bstate);
+    if (hipMemcpyAsync(c->d_binst, &I, sizeof(I), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->d_bstate, &st, sizeof(st), hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+      delete c;
+      return AA_EHIP;
+    }
+  }
   *ctx = c;
   return AA_OK;
 }
@@ -349,6 +446,7 @@ aa_status aa_set_stream(aa_ctx* c, void* stream) {
 aa_status aa_step(aa_ctx* c, const double* x, const double* g, double* x_next) {
   if (!c || !x || !g || !x_next || (c->flags & AA_QR_ONLY)) return AA_EINVAL;
   if (x_next == g) return AA_EINVAL;
+  if (c->d_binst && c->n <= c->fused_max) return fused_step(c, x, g, x_next);
   const hipStream_t st = c->stream;
   const int G = grid_stream(c);
   if (c->iter == 0) {
@@ -526,6 +624,12 @@ aa_status aa_profile_read(aa_ctx* c, int kind, double* ms, int64_t* launches, do
   if (ms) *ms = c->prof_ms[kind];
   if (launches) *launches = c->prof_launches[kind];
   if (bytes) *bytes = c->prof_bytes[kind];
+  return AA_OK;
+}
+
+aa_status aa_set_fused_threshold(aa_ctx* c, int64_t n_max) {
+  if (!c || n_max < 0) return AA_EINVAL;
+  c->fused_max = n_max;
   return AA_OK;
 }
 

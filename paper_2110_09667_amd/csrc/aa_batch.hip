@@ -238,7 +238,7 @@ __device__ BState wg_iteration(const BatchArgs& b, const BInst& I, BState st, L&
   const double res = sqrt(sm.scal[S_RES]);
   st.res_norm = res;
   st.status = *sm.status;
-  if (res <= b.tol * st.res0_norm || it >= b.max_iter || st.status != AA_OK) {
+  if (b.ov_iter < 0 && (res <= b.tol * st.res0_norm || it >= b.max_iter || st.status != AA_OK)) {
     st.active = 0;
     st.conv_iter = it;
     return st;
@@ -268,6 +268,15 @@ __global__ __launch_bounds__(kWG) void k_batch(BatchArgs b) {
   using L = BatchLds<KB, GRAM>;
   __shared__ L lds;
   __shared__ int s_idx;
+  if (b.ov_iter >= 0) {  // fused single-instance step: host-held counters
+    BState st = b.state[0];
+    st.iter = b.ov_iter;
+    st.k = b.ov_k;
+    st.active = 1;
+    const BState out = wg_iteration<KB, GRAM>(b, b.inst[0], st, lds);
+    if (threadIdx.x == 0) b.state[0] = out;
+    return;
+  }
   for (;;) {
     if (threadIdx.x == 0) s_idx = (int)atomicAdd(b.counter, 1u);
     __syncthreads();
@@ -287,6 +296,27 @@ __global__ void k_batch_reset(unsigned* counter) {
   if (threadIdx.x == 0) *counter = 0u;
 }
 
+// R = 0, T = I, coefficients, Givens, scalars and status cleared; one
+// workgroup per instance.
+__global__ void k_batch_init(BInst* inst, int count) {
+  const int j = blockIdx.x;
+  if (j >= count) return;
+  const Small sm = inst[j].sm;
+  const int cap = sm.cap;
+  for (int i = threadIdx.x; i < cap * cap; i += blockDim.x) {
+    sm.R[i] = 0.0;
+    sm.T[i] = ((i % cap) == (i / cap)) ? 1.0 : 0.0;
+  }
+  for (int i = threadIdx.x; i < 2 * cap; i += blockDim.x) sm.givens[i] = 0.0;
+  for (int i = threadIdx.x; i < cap; i += blockDim.x) {
+    sm.coef0[i] = 0.0;
+    sm.coef1[i] = 0.0;
+    sm.gamma[i] = 0.0;
+  }
+  if (threadIdx.x < S_COUNT) sm.scal[threadIdx.x] = 0.0;
+  if (threadIdx.x == 0) *sm.status = AA_OK;
+}
+
 template <bool GRAM>
 static hipError_t launch_kb(const BatchArgs& b, int grid, int kb, hipStream_t st) {
   switch (kb) {
@@ -302,6 +332,12 @@ static hipError_t launch_kb(const BatchArgs& b, int grid, int kb, hipStream_t st
 hipError_t launch_batch(const BatchArgs& b, int grid, int kbucket, bool gram, hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
   return gram ? launch_kb<true>(b, grid, kbucket, st) : launch_kb<false>(b, grid, kbucket, st);
+}
+
+hipError_t launch_batch_init(BInst* inst, int count, hipStream_t st) {
+  (void)hipGetLastError();  // drop a stale error left by an earlier call
+  hipLaunchKernelGGL(k_batch_init, dim3(count), dim3(kWG), 0, st, inst, count);
+  return hipGetLastError();
 }
 
 hipError_t launch_batch_reset(unsigned* counter, hipStream_t st) {

@@ -1,0 +1,277 @@
+// aa_batch_api.hip -- host side of the batched C ABI (aa_batch_* in aa.h).
+//
+// The workspace holds the instance descriptors, their device-updated states,
+// the schedule (instance order and work counter) and, per instance, G(x),
+// f_{i-1}, G(x_{i-1}), Delta f, Q, the Delta g history and the small dense
+// block.  aa_batch_run enqueues one persistent launch per iteration (after a
+// one-thread reset of the work counter); with a non-NULL stream the sequence
+// for a given iteration count is captured once as a HIP graph and replayed.
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "aa_internal.h"
+
+using namespace aa;
+
+struct aa_batch {
+  int count = 0, variant = 0;
+  unsigned flags = 0;
+  double tol = 0.0;
+  int64_t max_iter = 0;
+  hipStream_t stream = nullptr;
+  BInst* d_inst = nullptr;
+  BState* d_state = nullptr;
+  int* d_order = nullptr;
+  unsigned* d_counter = nullptr;
+  std::vector<int64_t> n;
+  std::vector<int> m;
+  int kbucket = 8;
+  bool gram = false;
+  int grid = 0;        // persistent workgroups (0: 2 per compute unit)
+  int order_mode = 0;  // 0: largest n*m first, 1: as given
+  bool use_graph = true;
+  hipGraphExec_t exec = nullptr;
+  int exec_iters = 0;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int64_t ld_of(int64_t n) { return (n + 63) / 64 * 64; }
+
+bool valid_instance(const aa_batch_instance& I) {
+  if (I.m < 1 || I.m > 64 || I.dim < 1 || I.dim > 3 || I.s < 1) return false;
+  int64_t n = I.s;
+  if (I.dim >= 2) n *= I.s;
+  if (I.dim >= 3) n *= I.s;
+  if (n != I.n || !(I.h > 0.0) || !I.d_f || !I.d_x) return false;
+  if (((uintptr_t)I.d_f % 16) != 0 || ((uintptr_t)I.d_x % 16) != 0) return false;
+  return true;
+}
+
+size_t instance_bytes(int64_t n, int m) {
+  const size_t vec = align_up((size_t)ld_of(n) * sizeof(double));
+  size_t b = 4 * vec + 2 * (size_t)m * vec;  // g, f_prev, g_prev, W, Q, ring
+  b += 2 * align_up(sizeof(double) * m * m);  // R, T
+  b += 3 * align_up(sizeof(double) * m);      // coef0, coef1, gamma
+  b += align_up(sizeof(double) * 2 * m);      // Givens
+  b += align_up(sizeof(double) * S_COUNT);    // scalars
+  b += align_up(sizeof(int));                 // status
+  return b;
+}
+
+size_t header_bytes(int count) {
+  return align_up(sizeof(BInst) * count) + align_up(sizeof(BState) * count) +
+         align_up(sizeof(int) * count) + align_up(sizeof(unsigned));
+}
+
+int bucket(int m) { return m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : 64; }
+
+hipError_t enqueue(aa_batch* b, int iters) {
+  BatchArgs a{};
+  a.inst = b->d_inst;
+  a.state = b->d_state;
+  a.order = b->d_order;
+  a.count = b->count;
+  a.counter = b->d_counter;
+  a.variant = b->variant;
+  a.flags = b->flags;
+  a.tol = b->tol;
+  a.max_iter = b->max_iter;
+  a.ov_iter = -1;
+  int grid = b->grid;
+  if (grid <= 0) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    grid = 2 * cus;
+  }
+  if (grid > b->count) grid = b->count;
+  for (int i = 0; i < iters; ++i) {
+    hipError_t e = launch_batch_reset(b->d_counter, b->stream);
+    if (e != hipSuccess) return e;
+    e = launch_batch(a, grid, b->kbucket, b->gram, b->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+void drop_graph(aa_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  b->exec = nullptr;
+  b->exec_iters = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+aa_status aa_batch_workspace_size(int count, const aa_batch_instance* inst, int variant,
+                                  unsigned flags, size_t* bytes) {
+  (void)flags;
+  if (count < 1 || !inst || !bytes || variant < AA_MGS || variant > AA_ICWY) return AA_EINVAL;
+  size_t tot = header_bytes(count);
+  for (int j = 0; j < count; ++j) {
+    if (!valid_instance(inst[j])) return AA_EINVAL;
+    tot += instance_bytes(inst[j].n, inst[j].m);
+  }
+  *bytes = tot;
+  return AA_OK;
+}
+
+aa_status aa_batch_init(aa_batch** out, int count, const aa_batch_instance* inst, int variant,
+                        unsigned flags, double tol, int64_t max_iter, void* d_ws,
+                        size_t bytes, void* stream) {
+  if (!out) return AA_EINVAL;
+  *out = nullptr;
+  size_t need = 0;
+  aa_status s = aa_batch_workspace_size(count, inst, variant, flags, &need);
+  if (s != AA_OK) return s;
+  if (!d_ws || ((uintptr_t)d_ws % kAlign) != 0 || !(tol >= 0.0) || max_iter < 1)
+    return AA_EINVAL;
+  if (bytes < need) return AA_ENOSPACE;
+  aa_batch* b = new (std::nothrow) aa_batch();
+  if (!b) return AA_EINVAL;
+  b->count = count;
+  b->variant = variant;
+  b->flags = flags;
+  b->tol = tol;
+  b->max_iter = max_iter;
+  b->stream = (hipStream_t)stream;
+  char* base = (char*)d_ws;
+  size_t o = 0;
+  b->d_inst = (BInst*)(base + o); o = align_up(o + sizeof(BInst) * count);
+  b->d_state = (BState*)(base + o); o = align_up(o + sizeof(BState) * count);
+  b->d_order = (int*)(base + o); o = align_up(o + sizeof(int) * count);
+  b->d_counter = (unsigned*)(base + o); o = align_up(o + sizeof(unsigned));
+  std::vector<BInst> hi(count);
+  std::vector<BState> hs(count);
+  int mmax = 1;
+  for (int j = 0; j < count; ++j) {
+    const aa_batch_instance& A = inst[j];
+    BInst& I = hi[j];
+    const int64_t ld = ld_of(A.n);
+    const size_t vec = align_up((size_t)ld * sizeof(double));
+    const int m = A.m;
+    I.n = A.n; I.ld = ld; I.m = m; I.dim = A.dim; I.s = A.s;
+    I.h = A.h; I.omega = A.omega; I.c = A.c;
+    I.f = A.d_f; I.x = A.d_x;
+    I.g = (double*)(base + o); o += vec;
+    I.f_prev = (double*)(base + o); o += vec;
+    I.g_prev = (double*)(base + o); o += vec;
+    I.W = (double*)(base + o); o += vec;
+    I.Q = (double*)(base + o); o += vec * m;
+    I.ring = (double*)(base + o); o += vec * m;
+    Small& sm = I.sm;
+    sm.R = (double*)(base + o); o = align_up(o + sizeof(double) * m * m);
+    sm.T = (double*)(base + o); o = align_up(o + sizeof(double) * m * m);
+    sm.coef0 = (double*)(base + o); o = align_up(o + sizeof(double) * m);
+    sm.coef1 = (double*)(base + o); o = align_up(o + sizeof(double) * m);
+    sm.gamma = (double*)(base + o); o = align_up(o + sizeof(double) * m);
+    sm.givens = (double*)(base + o); o = align_up(o + sizeof(double) * 2 * m);
+    sm.scal = (double*)(base + o); o = align_up(o + sizeof(double) * S_COUNT);
+    sm.status = (int*)(base + o); o = align_up(o + sizeof(int));
+    sm.partials = nullptr;
+    sm.cap = m;
+    BState& st = hs[j];
+    st.iter = 0; st.conv_iter = -1; st.k = 0; st.m_i = 0; st.active = 1; st.status = 0;
+    st.res_norm = st.res0_norm = 0.0;
+    b->n.push_back(A.n);
+    b->m.push_back(m);
+    mmax = std::max(mmax, m);
+  }
+  b->kbucket = bucket(mmax);
+  b->gram = variant == AA_ICWY;
+  hipError_t e = hipMemcpyAsync(b->d_inst, hi.data(), sizeof(BInst) * count,
+                                hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_state, hs.data(), sizeof(BState) * count, hipMemcpyHostToDevice,
+                       b->stream);
+  if (e == hipSuccess) e = launch_batch_init(b->d_inst, count, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) {
+    delete b;
+    return AA_EHIP;
+  }
+  if (aa_batch_set_schedule(b, 0, 0, 1) != AA_OK) {
+    delete b;
+    return AA_EHIP;
+  }
+  *out = b;
+  return AA_OK;
+}
+
+aa_status aa_batch_set_schedule(aa_batch* b, int grid, int order, int use_graph) {
+  if (!b || grid < 0 || grid > 65536 || order < 0 || order > 1) return AA_EINVAL;
+  std::vector<int> ord(b->count);
+  std::iota(ord.begin(), ord.end(), 0);
+  if (order == 0)
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) {
+      return b->n[a] * b->m[a] > b->n[c] * b->m[c];
+    });
+  if (hipMemcpyAsync(b->d_order, ord.data(), sizeof(int) * b->count, hipMemcpyHostToDevice,
+                     b->stream) != hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess)
+    return AA_EHIP;
+  b->grid = grid;
+  b->order_mode = order;
+  b->use_graph = use_graph != 0;
+  drop_graph(b);
+  return AA_OK;
+}
+
+aa_status aa_batch_run(aa_batch* b, int iters) {
+  if (!b || iters < 0) return AA_EINVAL;
+  if (iters == 0) return AA_OK;
+  if (!b->use_graph || b->stream == nullptr) return enqueue(b, iters) == hipSuccess ? AA_OK : AA_EHIP;
+  if (b->exec_iters != iters) {
+    drop_graph(b);
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return AA_EHIP;
+    hipError_t e = enqueue(b, iters);
+    hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return AA_EHIP;
+    }
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      b->exec = nullptr;
+      return AA_EHIP;
+    }
+    b->exec_iters = iters;
+  }
+  return hipGraphLaunch(b->exec, b->stream) == hipSuccess ? AA_OK : AA_EHIP;
+}
+
+aa_status aa_batch_read(aa_batch* b, aa_batch_state* states, int* active) {
+  if (!b) return AA_EINVAL;
+  std::vector<BState> hs(b->count);
+  if (hipMemcpyAsync(hs.data(), b->d_state, sizeof(BState) * b->count, hipMemcpyDeviceToHost,
+                     b->stream) != hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess)
+    return AA_EHIP;
+  if (states) memcpy(states, hs.data(), sizeof(BState) * b->count);
+  if (active) {
+    int a = 0;
+    for (const BState& st : hs) a += st.active ? 1 : 0;
+    *active = a;
+  }
+  return AA_OK;
+}
+
+aa_status aa_batch_destroy(aa_batch* b) {
+  if (!b) return AA_OK;
+  drop_graph(b);
+  delete b;
+  return AA_OK;
+}
+
+}  // extern "C"

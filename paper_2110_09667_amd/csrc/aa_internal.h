@@ -140,25 +140,29 @@ struct BInst {
   Small sm;               // R, T, coefficients, gamma, Givens, scalars, status
 };
 
-// Per-instance iteration state, updated on the device.
+// Per-instance iteration state, updated on the device (layout of aa_batch_state).
 struct BState {
   int64_t iter;           // index i of the next iteration
   int64_t conv_iter;      // iteration at which the instance stopped (-1: running)
   int k, m_i, active, status;
   double res_norm, res0_norm;
 };
+static_assert(sizeof(BState) == sizeof(aa_batch_state), "BState mirrors aa_batch_state");
 
 struct BatchArgs {
   BInst* inst; BState* state; const int* order; int count;
   unsigned* counter;      // work counter, reset before every launch
   int variant; unsigned flags;
   double tol; int64_t max_iter;
-  // single-instance override (count == 1, fused aa_step): x, G(x), x_next
+  // fused single-instance step (ov_iter >= 0): instance 0 only, with the
+  // caller's x, G(x), x_next and the host's iteration index and column count
   const double* ox; const double* og; double* oxn;
+  int64_t ov_iter; int ov_k;
 };
 
 hipError_t launch_batch(const BatchArgs&, int grid, int kbucket, bool gram, hipStream_t);
 hipError_t launch_batch_reset(unsigned* counter, hipStream_t);
+hipError_t launch_batch_init(BInst* inst, int count, hipStream_t);
 
 // launchers (aa_kernels.hip)
 hipError_t launch_dots(const DotsArgs&, const Small&, const Tail&, int grid, hipStream_t);

@@ -21,15 +21,18 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
 
 
-def gpu_aa_run(prob, m, variant, iters, flags=0, x0=None, record=True):
+def gpu_aa_run(prob, m, variant, iters, flags=0, x0=None, record=True, fused=None):
     """Run AA on the GPU with the library's stencil map; returns the iterates
-    x_0..x_{iters+1} (numpy) and the context."""
+    x_0..x_{iters+1} (numpy) and the context.  fused: None = library default
+    (one-workgroup step for small n), True = always, False = never."""
     import torch
     from paper_2110_09667_amd import aa
     dev = torch.device("cuda:0")
     n = prob.n
     f_d = to_dev(prob.f)
     ctx = aa.AAContext(n, m, variant, flags)
+    if fused is not None:
+        ctx.set_fused_threshold(1 << 40 if fused else 0)
     x = to_dev(np.zeros(n) if x0 is None else x0)
     g = torch.empty_like(x)
     xs = [x.cpu().numpy()]

@@ -241,13 +241,15 @@ def test_sync_counts_match_paper(variant):
 # ---------------------------------------------------------------- AA loops
 
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_aa_poisson1d_matches_oracle(variant):
-    """Linear 1D Poisson, n = 4096, m = 5: 20 iterations, iterate by iterate."""
+@pytest.mark.parametrize("fused", [True, False])
+def test_aa_poisson1d_matches_oracle(variant, fused):
+    """Linear 1D Poisson, n = 4096, m = 5: 20 iterations, iterate by iterate,
+    through the one-workgroup fused step and through the grid-wide passes."""
     device()
     prob = W.poisson1d()
     iters = 20
     xs_ref, st, res = O.run_aa(lambda u: O.G_stencil(prob, u), np.zeros(prob.n), 5, variant, iters)
-    xs, ctx = gpu_aa_run(prob, 5, variant, iters)
+    xs, ctx = gpu_aa_run(prob, 5, variant, iters, fused=fused)
     for i in range(1, iters + 2):
         assert rel(xs[i], xs_ref[i]) <= 1e-10, (i, rel(xs[i], xs_ref[i]))
     info = ctx.info()
@@ -259,14 +261,15 @@ def test_aa_poisson1d_matches_oracle(variant):
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
-@pytest.mark.parametrize("m", [1, 3, 10])
-def test_aa_nonlinear3d_small_matches_oracle(variant, m):
+@pytest.mark.parametrize("m", [1, 3, 10, 17])
+@pytest.mark.parametrize("fused", [True, False])
+def test_aa_nonlinear3d_small_matches_oracle(variant, m, fused):
     """3D nonlinear map on a 21^3 grid (several tiles, ragged), 20 iterations."""
     device()
     prob = W.nonlinear3d(s=21, seed=6)
     iters = 20
     xs_ref, _, _ = O.run_aa(lambda u: O.G_stencil(prob, u), np.zeros(prob.n), m, variant, iters)
-    xs, ctx = gpu_aa_run(prob, m, variant, iters)
+    xs, ctx = gpu_aa_run(prob, m, variant, iters, fused=fused)
     worst = max(rel(xs[i], xs_ref[i]) for i in range(1, iters + 2))
     assert worst <= 1e-10, worst
     assert ctx.info().status == 0
@@ -281,9 +284,10 @@ def test_aa_tiny_and_secant(variant):
     for s, m, iters in ((1, 1, 4), (7, 3, 8)):
         prob = W.StencilProblem(d=1, s=s, c=0.3, f=W.uniform(3, 1, s))
         xs_ref, _, _ = O.run_aa(lambda u: O.G_stencil(prob, u), np.zeros(s), m, variant, iters)
-        xs, _ = gpu_aa_run(prob, m, variant, iters)
-        for i in range(1, iters + 2):
-            assert rel(xs[i], xs_ref[i]) <= 1e-10, (s, i)
+        for fused in (True, False):
+            xs, _ = gpu_aa_run(prob, m, variant, iters, fused=fused)
+            for i in range(1, iters + 2):
+                assert rel(xs[i], xs_ref[i]) <= 1e-10, (s, i, fused)
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
