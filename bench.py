@@ -183,7 +183,21 @@ def main():
     ap.add_argument("--no-other-variants", action="store_true")
     ap.add_argument("--grid", type=int, nargs=2, default=None,
                     help="max workgroups: streaming passes, Gram pass")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (5 times), to "
+                         "calibrate the HBM byte counters of a profiler")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
+                          "repeats": 5}), flush=True)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "

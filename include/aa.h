@@ -174,8 +174,8 @@ aa_status aa_profile_read(aa_ctx *ctx, int kind, double *ms, int64_t *launches,
 aa_status aa_profile_reset(aa_ctx *ctx);
 
 /* Upper bounds on the workgroups of the streaming passes and of the ICWY
- * Gram pass (defaults 1024 and 256; each in [1, 4096], and the Gram bound
- * times (m-1)(m-2)/2 may not exceed 134 * 4096). */
+ * Gram pass (defaults 1024 and 1024; each in [1, 4096]; the Gram pass also
+ * keeps (workgroups) x (k-1)(k-2)/2 within its partials buffer). */
 aa_status aa_set_grid(aa_ctx *ctx, int stream_max, int gram_max);
 
 /* Largest n for which aa_step runs the whole iteration in one workgroup (one

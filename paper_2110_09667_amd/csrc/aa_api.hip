@@ -27,7 +27,7 @@ struct aa_ctx {
   double* g_prev = nullptr; // ldq, AA only
   Small sm{};
   int grid_stream_max = 1024;  // workgroups of the streaming passes
-  int grid_gram_max = 256;     // workgroups of the ICWY Gram pass
+  int grid_gram_max = 1024;    // workgroups of the ICWY Gram pass
   int64_t iter = 0;
   int k = 0, m_i = 0;
   int64_t syncs_add = 0, syncs_del = 0, syncs_rhs = 0;
@@ -273,7 +273,13 @@ aa_status qr_delete_impl(aa_ctx* c) {
   if (e != hipSuccess) return AA_EHIP;
   const bool gram = c->variant == AA_ICWY;
   RotArgs r{c->Q, c->ldq, c->n, k, c->sm.givens, gram ? 1 : 0};
-  const int G = grid_rows(c, gram ? c->grid_gram_max : c->grid_stream_max);
+  int gmax = c->grid_stream_max;
+  if (gram) {  // (k-1)(k-2)/2 pair sums per workgroup must fit the partials
+    const int64_t pairs = (int64_t)(k - 1) * (k - 2) / 2;
+    const int64_t cap = pairs > 0 ? (int64_t)kPartials / pairs : c->grid_gram_max;
+    gmax = (int)(c->grid_gram_max < cap ? c->grid_gram_max : cap);
+  }
+  const int G = grid_rows(c, gmax);
   e = timed(c, AA_K_ROTATE, 2 * k - 1,
             [&] { return launch_rotate(r, c->sm, tail(TAIL_GRAM, k - 1), G, c->stream); });
   if (e != hipSuccess) return AA_EHIP;
@@ -636,10 +642,9 @@ aa_status aa_set_fused_threshold(aa_ctx* c, int64_t n_max) {
 aa_status aa_set_grid(aa_ctx* c, int stream_max, int gram_max) {
   if (!c || stream_max < 1 || stream_max > 4096 || gram_max < 1 || gram_max > 4096)
     return AA_EINVAL;
-  // every pass publishes (values reduced) x (workgroups) partials
-  const size_t gram_vals = (size_t)(c->m - 1) * (c->m - 2) / 2 + 1;
-  if ((size_t)stream_max * kMaxRed > kPartials || (size_t)gram_max * gram_vals > kPartials)
-    return AA_EINVAL;
+  // every pass publishes (values reduced) x (workgroups) partials; the Gram
+  // pass clamps its grid to the partials buffer by itself
+  if ((size_t)stream_max * kMaxRed > kPartials) return AA_EINVAL;
   c->grid_stream_max = stream_max;
   c->grid_gram_max = gram_max;
   return AA_OK;

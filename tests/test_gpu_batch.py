@@ -41,7 +41,9 @@ def test_batch_matches_oracle(variant):
         assert rel(got, xs[-1]) <= 1e-10, (j, inst, rel(got, xs[-1]))
         assert states[j].iter == iters + 1 and states[j].k == min(inst.m, iters)
         assert states[j].status == 0
-        assert abs(states[j].res_norm - st.res_norm) <= 1e-10 * st.res_norm
+        # ||f_i|| is a difference of nearly equal vectors once converged: its
+        # rounding is relative to ||f_0||, not to itself
+        assert abs(states[j].res_norm - st.res_norm) <= 1e-10 * st.res0_norm
 
 
 @pytest.mark.parametrize("variant", ["icwy", "mgs"])
@@ -93,14 +95,17 @@ def test_batch_schedule_does_not_change_results():
 def test_batch_stops_at_tolerance(variant):
     """Each instance stops at the first i with ||f_i|| <= 1e-8 ||f_0||; the
     oracle with the same rule stops within one iteration of it (rounding can
-    move a borderline residual across the threshold)."""
+    move a borderline residual across the threshold).  An instance that has
+    not converged by max_iter stops there."""
     device()
     from paper_2110_09667_amd import aa
-    insts, probs = small_table(count=8, seed0=300)
-    b = aa.AABatch(probs, [i.m for i in insts], variant, tol=1e-8, max_iter=400)
+    insts = W.batch_table(8, first_seed=300, s_lo=5, s_hi=40, m_lo=3, m_hi=12)
+    probs = [W.batch_problem(i) for i in insts]
+    cap = 600
+    b = aa.AABatch(probs, [i.m for i in insts], variant, tol=1e-8, max_iter=cap)
     b.set_schedule(use_graph=False)
-    for _ in range(40):
-        b.run(10)
+    for _ in range(cap // 20 + 2):
+        b.run(20)
         _, active = b.read()
         if active == 0:
             break
@@ -108,11 +113,14 @@ def test_batch_stops_at_tolerance(variant):
     assert active == 0
     for j, (inst, p) in enumerate(zip(insts, probs)):
         _, st, res = O.run_aa(lambda u: O.G_stencil(p, u), np.zeros(p.n), inst.m, variant,
-                              iters=400, tol=1e-8)
+                              iters=cap, tol=1e-8)
         oracle_stop = len(res) - 1
-        assert states[j].stop_iter >= 1
-        assert abs(states[j].stop_iter - oracle_stop) <= 1, (j, states[j].stop_iter, oracle_stop)
-        assert states[j].res_norm <= 1e-8 * states[j].res0_norm
+        assert 1 <= states[j].stop_iter <= cap
+        if oracle_stop < cap - 1:
+            assert abs(states[j].stop_iter - oracle_stop) <= 1, (j, states[j].stop_iter, oracle_stop)
+            assert states[j].res_norm <= 1e-8 * states[j].res0_norm
+        else:
+            assert states[j].stop_iter >= cap - 1
 
 
 def test_batch_mixed_sizes_with_a_large_instance():

@@ -120,14 +120,19 @@ def test_qr_add_wide_bases(variant, k):
     n = 3 * 2048 + 301
     m = k + 1
     ctx, ref = qr_pair(n, m, variant)
-    F = graded(n, m, 1e4, seed=100 + k)
+    kappa = 1e4
+    F = graded(n, m, kappa, seed=100 + k)
     for t in range(m):
         ref.add(F[:, t])
         ctx.qr_add(to_dev(F[:, t]))
-    compare_qr(ctx, ref, 1e-11)
+    # DCGS-2's newest column is orthogonalized once (its reorthogonalization
+    # is delayed to the next add), so two roundings of it differ by O(eps)
+    # kappa; the other variants reorthogonalize or project sequentially
+    tol = 100 * EPS * kappa if variant == "dcgs2" else 1e-11
+    compare_qr(ctx, ref, tol)
     ref.delete()
     ctx.qr_delete()
-    compare_qr(ctx, ref, 1e-11)
+    compare_qr(ctx, ref, tol)
 
 
 @pytest.mark.parametrize("k", [5, 12, 20, 33, 47, 64])
