@@ -239,6 +239,43 @@ aa_status aa_batch_set_schedule(aa_batch *b, int grid, int order, int use_graph)
 
 aa_status aa_batch_destroy(aa_batch *b);
 
+/* ---------------- the learned mixing-weight network ---------------------- */
+
+/* A small network that reads the n-independent state of the windowed QR --
+ * the upper triangle of R and c = Q^T f_i, zero-padded to a 20-column window
+ * and divided by ||f_i|| (230 features) -- and proposes a correction to the
+ * mixing weights gamma (20 outputs) and a damping logit (1 output):
+ * 230 -> 256 -> 256 -> 256 -> 21, GELU (erf form), BF16 operands on the
+ * matrix cores with FP32 accumulation, FP32 master weights, Adam.  Not part
+ * of the paper: an addition that never replaces the FP64 method (see the
+ * guarded batched step). */
+#define AA_MLP_FEATURES 230
+#define AA_MLP_OUTPUTS 21
+typedef struct aa_mlp aa_mlp;
+
+/* Parameters in the packed order W0 [256 x 256], b0 [256], W1, b1, W2, b2,
+ * W3 [256 x 64], b3 [64] (row-major; inputs 230..255 and outputs 21..63 are
+ * padding and stay zero). */
+int64_t aa_mlp_param_count(void);
+aa_status aa_mlp_workspace_size(int max_batch, size_t *bytes);
+/* Seeded initialization: hidden layers N(0, 2/fan_in), last layer zero with
+ * the damping-logit bias at +4 (no correction, beta = sigmoid(4)). */
+aa_status aa_mlp_init(aa_mlp **net, int max_batch, uint64_t seed, void *d_workspace,
+                      size_t bytes, void *stream);
+aa_status aa_mlp_reseed(aa_mlp *net, uint64_t seed);
+aa_status aa_mlp_set_params(aa_mlp *net, const float *h_params);  /* waits */
+aa_status aa_mlp_get_params(aa_mlp *net, float *h_params);        /* waits */
+aa_status aa_mlp_get_grads(aa_mlp *net, float *h_grads);          /* waits */
+/* d_x: batch x 230 FP32 features; d_out: batch x 21 FP32 outputs (may be
+ * NULL).  Keeps the activations for aa_mlp_backward. */
+aa_status aa_mlp_forward(aa_mlp *net, int batch, const float *d_x, float *d_out);
+/* d_dout: batch x 21 gradient of the loss w.r.t. the outputs of the last
+ * forward (same batch); accumulates the parameter gradients. */
+aa_status aa_mlp_backward(aa_mlp *net, int batch, const float *d_dout);
+/* One Adam step with the accumulated gradients, which are then cleared. */
+aa_status aa_mlp_adam(aa_mlp *net, float lr, float beta1, float beta2, float eps);
+aa_status aa_mlp_destroy(aa_mlp *net);
+
 /* ---------------- model fixed-point maps and seeded inputs --------------- */
 
 /* d_out = d_u - omega (A d_u + c d_u^3 - d_f), A the (2 dim + 1)-point

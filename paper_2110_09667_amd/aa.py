@@ -30,7 +30,10 @@ SYMBOLS = [
     "aa_fill_uniform", "aa_fill_normal", "aa_version", "aa_profile_enable",
     "aa_profile_read", "aa_profile_reset", "aa_set_grid", "aa_set_fused_threshold",
     "aa_batch_workspace_size", "aa_batch_init", "aa_batch_run", "aa_batch_read",
-    "aa_batch_set_schedule", "aa_batch_destroy",
+    "aa_batch_set_schedule", "aa_batch_destroy", "aa_mlp_param_count",
+    "aa_mlp_workspace_size", "aa_mlp_init", "aa_mlp_reseed", "aa_mlp_set_params",
+    "aa_mlp_get_params", "aa_mlp_get_grads", "aa_mlp_forward", "aa_mlp_backward",
+    "aa_mlp_adam", "aa_mlp_destroy",
 ]
 
 KERNEL_KINDS = ["dots", "update", "cgs2b", "givens", "rotate", "scale", "history", "xupdate",
@@ -104,11 +107,23 @@ def lib():
         "aa_batch_read": [P, C.POINTER(BatchState), C.POINTER(I)],
         "aa_batch_set_schedule": [P, I, I, I],
         "aa_batch_destroy": [P],
+        "aa_mlp_workspace_size": [I, C.POINTER(C.c_size_t)],
+        "aa_mlp_init": [C.POINTER(P), I, U64, P, C.c_size_t, P],
+        "aa_mlp_reseed": [P, U64],
+        "aa_mlp_set_params": [P, P],
+        "aa_mlp_get_params": [P, P],
+        "aa_mlp_get_grads": [P, P],
+        "aa_mlp_forward": [P, I, P, P],
+        "aa_mlp_backward": [P, I, P],
+        "aa_mlp_adam": [P, C.c_float, C.c_float, C.c_float, C.c_float],
+        "aa_mlp_destroy": [P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = C.c_int
+    L.aa_mlp_param_count.argtypes = []
+    L.aa_mlp_param_count.restype = C.c_int64
     L.aa_version.argtypes = []
     L.aa_version.restype = C.c_char_p
     _lib = L
@@ -399,6 +414,65 @@ class AABatch:
         if getattr(self, "b", None) is not None:
             aa_batch_destroy(self.b)
             self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+MLP_FEATURES, MLP_OUTPUTS = 230, 21
+
+
+class AAMlp:
+    """The mixing-weight network (BF16 MFMA kernels) with its own workspace."""
+
+    def __init__(self, max_batch: int, seed: int = 0, stream=None, device="cuda"):
+        import torch
+        b = C.c_size_t(0)
+        _check(lib().aa_mlp_workspace_size(max_batch, C.byref(b)), "aa_mlp_workspace_size")
+        self.workspace = torch.empty((b.value + 7) // 8, dtype=torch.float64, device=device)
+        self.net = C.c_void_p()
+        _check(lib().aa_mlp_init(C.byref(self.net), max_batch, seed, self.workspace.data_ptr(),
+                                 b.value, _stream(stream)), "aa_mlp_init")
+        self.P = lib().aa_mlp_param_count()
+
+    def set_params(self, params):
+        import numpy as np
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        assert a.size == self.P
+        _check(lib().aa_mlp_set_params(self.net, a.ctypes.data), "aa_mlp_set_params")
+
+    def get_params(self):
+        import numpy as np
+        a = np.empty(self.P, dtype=np.float32)
+        _check(lib().aa_mlp_get_params(self.net, a.ctypes.data), "aa_mlp_get_params")
+        return a
+
+    def get_grads(self):
+        import numpy as np
+        a = np.empty(self.P, dtype=np.float32)
+        _check(lib().aa_mlp_get_grads(self.net, a.ctypes.data), "aa_mlp_get_grads")
+        return a
+
+    def forward(self, x, out=None):
+        _check(lib().aa_mlp_forward(self.net, x.shape[0], x.data_ptr(), _ptr(out)),
+               "aa_mlp_forward")
+
+    def backward(self, dout):
+        _check(lib().aa_mlp_backward(self.net, dout.shape[0], dout.data_ptr()), "aa_mlp_backward")
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        _check(lib().aa_mlp_adam(self.net, lr, b1, b2, eps), "aa_mlp_adam")
+
+    def reseed(self, seed: int):
+        _check(lib().aa_mlp_reseed(self.net, seed), "aa_mlp_reseed")
+
+    def close(self):
+        if getattr(self, "net", None) is not None and self.net.value:
+            _check(lib().aa_mlp_destroy(self.net), "aa_mlp_destroy")
+            self.net = None
 
     def __del__(self):
         try:

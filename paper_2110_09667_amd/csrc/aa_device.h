@@ -112,4 +112,25 @@ __device__ __forceinline__ void axpy2(double2 (&acc)[kPairs], const double2 (&q)
 #endif
 constexpr int kGroup = AA_GROUP;  // Q columns loaded together (kGroup * kPairs loads in flight)
 
+// SplitMix64 (Steele, Lea, Flood 2014): output function of z + golden gamma;
+// the library's seeded streams evaluate it at a per-stream origin plus i.
+__host__ __device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+inline uint64_t sm64_mix_host(uint64_t z) { return sm64_mix(z); }
+
+__device__ __forceinline__ double u01(uint64_t z) {
+  return (double)(sm64_mix(z) >> 11) * 0x1.0p-53;
+}
+
+// Standard normal from counter pair (2e, 2e + 1) of a stream: Box-Muller,
+// cosine branch.
+__device__ __forceinline__ double normal_at(uint64_t base, uint64_t e) {
+  const double u1 = u01(base + 2 * e), u2 = u01(base + 2 * e + 1);
+  return sqrt(-2.0 * log1p(-u1)) * cos(6.283185307179586476925286766559 * u2);
+}
+
 }  // namespace aa

@@ -31,28 +31,9 @@ hipError_t launch_stencil(int dim, int64_t s, double h, double omega, double c,
   return hipGetLastError();
 }
 
-// SplitMix64 (Steele, Lea, Flood 2014): output function of z + golden gamma.
-__device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
-  z += 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
-static uint64_t sm64_mix_host(uint64_t z) {
-  z += 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
 // counter origin of stream (seed, stream_id)
 static uint64_t stream_base(uint64_t seed, uint64_t stream_id) {
   return sm64_mix_host(sm64_mix_host(seed) + stream_id);
-}
-
-__device__ __forceinline__ double u01(uint64_t z) {
-  return (double)(sm64_mix(z) >> 11) * 0x1.0p-53;
 }
 
 __global__ void k_fill_uniform(double* out, int64_t n, uint64_t base, double lo, double hi) {
@@ -62,13 +43,9 @@ __global__ void k_fill_uniform(double* out, int64_t n, uint64_t base, double lo,
 }
 
 __global__ void k_fill_normal(double* out, int64_t n, uint64_t base, uint64_t offset) {
-  const double two_pi = 6.283185307179586476925286766559;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t e = 2 * (offset + (uint64_t)i);
-    const double u1 = u01(base + e), u2 = u01(base + e + 1);
-    out[i] = sqrt(-2.0 * log1p(-u1)) * cos(two_pi * u2);
-  }
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = normal_at(base, offset + (uint64_t)i);
 }
 
 hipError_t launch_fill_uniform(double* out, int64_t n, uint64_t seed, uint64_t stream_id,
