@@ -42,6 +42,8 @@ extern "C" {
 #endif
 
 typedef struct aa_ctx aa_ctx;
+typedef struct aa_batch aa_batch;
+typedef struct aa_mlp aa_mlp;
 
 /* QRAdd variants (Sec. 3): Alg. 3, Alg. 5, Alg. 6, Alg. 4. */
 typedef enum { AA_MGS = 0, AA_CGS2 = 1, AA_DCGS2 = 2, AA_ICWY = 3 } aa_variant;
@@ -192,8 +194,6 @@ aa_status aa_set_fused_threshold(aa_ctx *ctx, int64_t n_max);
  * Sync of Sec. 3 becomes a workgroup barrier.  An instance stops (and is
  * skipped from then on) when ||f_i|| <= tol ||f_0|| at the start of iteration
  * i, when i reaches max_iter, or on breakdown. */
-typedef struct aa_batch aa_batch;
-
 typedef struct {
   int64_t n;          /* vector length; n = s^dim                             */
   int m;              /* window, 1 <= m <= 64                                 */
@@ -212,7 +212,17 @@ typedef struct {
   int k, m_i, active, status;
   double res_norm;    /* ||f_i||_2 at the last history formation              */
   double res0_norm;   /* ||f_0||_2                                            */
+  int64_t g_evals;    /* evaluations of G so far                              */
+  int64_t accepted;   /* learned candidates accepted by the guard             */
+  double loss;        /* last training loss sample of this instance           */
+  int pending;        /* internal: iteration split across the network call    */
+  int g_valid;        /* internal: G(x_i) already known (accepted candidate)  */
 } aa_batch_state;
+
+/* aa_batch_init flag: also allocate the learned step's candidate vectors and
+ * feature / output buffers (required by aa_batch_run_learned and
+ * aa_batch_train). */
+enum { AA_BATCH_LEARNED = 1u << 9 };
 
 aa_status aa_batch_workspace_size(int count, const aa_batch_instance *h_inst,
                                   int variant, unsigned flags, size_t *bytes);
@@ -237,6 +247,26 @@ aa_status aa_batch_read(aa_batch *b, aa_batch_state *h_states, int *h_active);
  * 1 = as given), graph replay on/off. */
 aa_status aa_batch_set_schedule(aa_batch *b, int grid, int order, int use_graph);
 
+/* Learned-guarded iterations (not part of the paper): after R gamma = Q^T f_i
+ * the network proposes delta gamma and beta from R and Q^T f_i; the candidate
+ * x_c = G(x_i) - G_i gamma' - (1 - beta)(f_i - Q R gamma'), gamma' = gamma +
+ * delta gamma, is accepted iff ||G(x_c) - x_c|| < ||f_i|| (then G(x_c) serves
+ * as G(x_{i+1})); otherwise the plain AA step x_{i+1} = G(x_i) - G_i gamma is
+ * taken.  net must have max_batch >= count; the batch needs AA_BATCH_LEARNED. */
+aa_status aa_batch_run_learned(aa_batch *b, aa_mlp *net, int iters);
+
+/* Training iterations: plain AA steps (the trajectory the network learns
+ * from); at each one the candidate's one-step loss log(||G(x_c)-x_c||^2 /
+ * ||f_i||^2) is back-propagated through G (the adjoint of the symmetric
+ * stencil map) into delta gamma and beta, then through the network, and one
+ * Adam step (learning rate lr) is taken per iteration. */
+aa_status aa_batch_train(aa_batch *b, aa_mlp *net, int iters, float lr);
+
+/* Copy the learned step's buffers of the last iteration (count x 230
+ * features, count x 21 network outputs, count x 21 loss gradients w.r.t. the
+ * outputs, each may be NULL).  Waits. */
+aa_status aa_batch_read_learning(aa_batch *b, float *h_feat, float *h_out, float *h_dout);
+
 aa_status aa_batch_destroy(aa_batch *b);
 
 /* ---------------- the learned mixing-weight network ---------------------- */
@@ -251,7 +281,6 @@ aa_status aa_batch_destroy(aa_batch *b);
  * guarded batched step). */
 #define AA_MLP_FEATURES 230
 #define AA_MLP_OUTPUTS 21
-typedef struct aa_mlp aa_mlp;
 
 /* Parameters in the packed order W0 [256 x 256], b0 [256], W1, b1, W2, b2,
  * W3 [256 x 64], b3 [64] (row-major; inputs 230..255 and outputs 21..63 are

@@ -287,3 +287,28 @@ def run_aa(G, x0, m: int, variant="mgs", iters: int = 20, flags: int = 0,
         if record:
             xs.append(x.copy())
     return xs, st, res
+
+
+# --------------------------------------------------------------------------
+# learned-guarded step (an addition to the paper's method, used to pin the
+# GPU training gradient): candidate and one-step loss from the oracle's state
+# --------------------------------------------------------------------------
+
+def learned_candidate(st: "AA", g: np.ndarray, dgamma: np.ndarray, beta: float) -> np.ndarray:
+    """x_c = G(x_i) - G_i gamma' - (1 - beta)(f_i - Q R gamma'), gamma' = gamma +
+    dgamma, from the state right after the oracle's step i (its gamma, Q, R,
+    window of Delta g and f_i)."""
+    gp = st.gamma_k() + dgamma[: st.m_i]
+    Fg = st.Qk() @ (st.Rk() @ gp)
+    return g - st.Gmat() @ gp - (1.0 - beta) * (st.f - Fg)
+
+
+def learned_loss(prob, st: "AA", g: np.ndarray, outputs: np.ndarray) -> float:
+    """log(||G(x_c) - x_c||^2 / ||f_i||^2) for network outputs (delta gamma in
+    outputs[:20] masked to m_i, beta = sigmoid(outputs[20]))."""
+    dg = np.zeros(20)
+    dg[: st.m_i] = outputs[: st.m_i]
+    beta = 1.0 / (1.0 + np.exp(-outputs[20]))
+    xc = learned_candidate(st, g, dg, beta)
+    r = G_stencil(prob, xc) - xc
+    return float(np.log(np.dot(r, r) / np.dot(st.f, st.f)))

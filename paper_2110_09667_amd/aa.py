@@ -33,8 +33,11 @@ SYMBOLS = [
     "aa_batch_set_schedule", "aa_batch_destroy", "aa_mlp_param_count",
     "aa_mlp_workspace_size", "aa_mlp_init", "aa_mlp_reseed", "aa_mlp_set_params",
     "aa_mlp_get_params", "aa_mlp_get_grads", "aa_mlp_forward", "aa_mlp_backward",
-    "aa_mlp_adam", "aa_mlp_destroy",
+    "aa_mlp_adam", "aa_mlp_destroy", "aa_batch_run_learned", "aa_batch_train",
+    "aa_batch_read_learning",
 ]
+
+BATCH_LEARNED = 1 << 9
 
 KERNEL_KINDS = ["dots", "update", "cgs2b", "givens", "rotate", "scale", "history", "xupdate",
                 "fused"]
@@ -61,7 +64,9 @@ class BatchInstance(C.Structure):
 class BatchState(C.Structure):
     _fields_ = [("iter", C.c_int64), ("stop_iter", C.c_int64), ("k", C.c_int),
                 ("m_i", C.c_int), ("active", C.c_int), ("status", C.c_int),
-                ("res_norm", C.c_double), ("res0_norm", C.c_double)]
+                ("res_norm", C.c_double), ("res0_norm", C.c_double),
+                ("g_evals", C.c_int64), ("accepted", C.c_int64), ("loss", C.c_double),
+                ("pending", C.c_int), ("g_valid", C.c_int)]
 
 
 _lib = None
@@ -117,6 +122,9 @@ def lib():
         "aa_mlp_backward": [P, I, P],
         "aa_mlp_adam": [P, C.c_float, C.c_float, C.c_float, C.c_float],
         "aa_mlp_destroy": [P],
+        "aa_batch_run_learned": [P, P, I],
+        "aa_batch_train": [P, P, I, C.c_float],
+        "aa_batch_read_learning": [P, P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -409,6 +417,22 @@ class AABatch:
 
     def set_schedule(self, grid: int = 0, order: int = 0, use_graph: bool = True):
         aa_batch_set_schedule(self.b, grid, order, use_graph)
+
+    def run_learned(self, net, iters: int):
+        _check(lib().aa_batch_run_learned(self.b, net.net, iters), "aa_batch_run_learned")
+
+    def train(self, net, iters: int, lr: float = 1e-3):
+        _check(lib().aa_batch_train(self.b, net.net, iters, lr), "aa_batch_train")
+
+    def read_learning(self):
+        """(features [count x 230], outputs [count x 21], dL/doutputs [count x 21])."""
+        import numpy as np
+        f = np.empty((self.count, 230), dtype=np.float32)
+        o = np.empty((self.count, 21), dtype=np.float32)
+        d = np.empty((self.count, 21), dtype=np.float32)
+        _check(lib().aa_batch_read_learning(self.b, f.ctypes.data, o.ctypes.data, d.ctypes.data),
+               "aa_batch_read_learning")
+        return f, o, d
 
     def close(self):
         if getattr(self, "b", None) is not None:

@@ -205,21 +205,23 @@ __device__ void wg_qr_delete(const BInst& I, int variant, int k, L& lds) {
   __syncthreads();
 }
 
-// One iteration of Alg. 1 for one instance (every thread of the workgroup).
-// it, k: iteration index and column count on entry.  Returns the new state.
+// Front of one iteration of Alg. 1 for one instance (every thread of the
+// workgroup): G, history formation, the stopping test, QRDelete, QRAdd and
+// R gamma = Q^T f_i.  Returns false when the iteration ends here (the first
+// step x_1 = G(x_0), or the instance stopped).
 template <int KB, bool GRAM, class L>
-__device__ BState wg_iteration(const BatchArgs& b, const BInst& I, BState st, L& lds) {
+__device__ bool wg_front(const BatchArgs& b, const BInst& I, BState& st, L& lds,
+                         const double* x, double* xn, const double* g) {
   const int tid = threadIdx.x;
   const Small& sm = I.sm;
-  const double* x = b.ox ? b.ox : I.x;
-  double* xn = b.oxn ? b.oxn : I.x;
-  const double* g = b.og ? b.og : I.g;
-  if (!b.og && I.dim > 0) {
+  if (!b.og && I.dim > 0 && !st.g_valid) {
     const double ih2 = 1.0 / (I.h * I.h);
     for (int64_t p = tid; p < I.n; p += kWG)
       I.g[p] = stencil_point(x, I.f, I.dim, I.s, ih2, I.omega, I.c, p);
     __syncthreads();
+    st.g_evals += 1;
   }
+  st.g_valid = 0;
   const int64_t it = st.iter;
   if (it == 0) {
     // Alg. 1 before the loop: x_1 = G(x_0), f_0 = G(x_0) - x_0
@@ -228,7 +230,7 @@ __device__ BState wg_iteration(const BatchArgs& b, const BInst& I, BState st, L&
     st.iter = 1;
     st.m_i = 0;
     st.res_norm = st.res0_norm = sqrt(sm.scal[S_RES]);
-    return st;
+    return false;
   }
   const int m = I.m;
   const int m_i = (int)(it < m ? it : m);
@@ -241,7 +243,7 @@ __device__ BState wg_iteration(const BatchArgs& b, const BInst& I, BState st, L&
   if (b.ov_iter < 0 && (res <= b.tol * st.res0_norm || it >= b.max_iter || st.status != AA_OK)) {
     st.active = 0;
     st.conv_iter = it;
-    return st;
+    return false;
   }
   int k = st.k;
   if (it > m) {
@@ -252,15 +254,236 @@ __device__ BState wg_iteration(const BatchArgs& b, const BInst& I, BState st, L&
   k += 1;
   DotsArgs d{I.Q, I.ld, I.n, I.f_prev, k, nullptr, 0, 0};
   wg_pass(sm, mk_tail(TAIL_RHS, k), k, lds, [&](double* acc) { dots_body(d, 0, 1, acc); });
-  XupdArgs xa{I.ring, I.ld, m, (int)((it - m_i) % m), m_i, g, x, xn, I.n, sm.gamma};
-  xupdate_coefs(xa, lds.sg, lds.sslot);
-  wg_pass(sm, mk_tail(TAIL_STEP, 0), 1, lds,
-          [&](double* acc) { xupdate_body(xa, lds.sg, lds.sslot, 0, 1, acc); });
-  st.iter = it + 1;
   st.k = k;
   st.m_i = m_i;
   st.status = *sm.status;
-  return st;
+  return true;
+}
+
+// x_{i+1} = G(x_i) - sum_j gamma_j Delta g_{i-m_i+j}  (the plain AA update).
+template <class L>
+__device__ void wg_plain_update(const BInst& I, const BState& st, L& lds, const double* x,
+                                double* xn, const double* g) {
+  const int64_t it = st.iter;
+  const int m = I.m, m_i = st.m_i;
+  XupdArgs xa{I.ring, I.ld, m, (int)((it - m_i) % m), m_i, g, x, xn, I.n, I.sm.gamma};
+  xupdate_coefs(xa, lds.sg, lds.sslot);
+  wg_pass(I.sm, mk_tail(TAIL_STEP, 0), 1, lds,
+          [&](double* acc) { xupdate_body(xa, lds.sg, lds.sslot, 0, 1, acc); });
+}
+
+// Network features of the current state: upper triangle of R over a 20-column
+// window (row-major, a <= b), then c = Q^T f_i, both divided by ||f_i||.
+__device__ void write_features(const BInst& I, const BState& st, float* row, bool live) {
+  const Small& sm = I.sm;
+  const int k = st.k;
+  const double inv = live ? 1.0 / st.res_norm : 0.0;
+  for (int t = threadIdx.x; t < kFeat; t += kWG) {
+    double v = 0.0;
+    if (live) {
+      if (t < kWin * (kWin + 1) / 2) {
+        int a = 0, rem = t;
+        while (rem >= kWin - a) {
+          rem -= kWin - a;
+          ++a;
+        }
+        const int bcol = a + rem;
+        if (bcol < k) v = sm.R[a + (size_t)bcol * sm.cap];
+      } else {
+        const int j = t - kWin * (kWin + 1) / 2;
+        if (j < k) v = sm.coef1[j];
+      }
+    }
+    row[t] = (float)(v * inv);
+  }
+}
+
+// The learned candidate: gamma' = gamma + delta gamma (first m_i outputs),
+// beta = sigmoid(o_20), w = R gamma', x_c = g - G_i gamma' - (1 - beta)(f_i - Q w)
+// into I.xc; then G(x_c) into I.gc.  Leaves gamma' in lds.c1, w in lds.c2,
+// slot order in lds.sslot; returns beta.
+template <class L>
+__device__ double wg_candidate(const BatchArgs& b, const BInst& I, const BState& st, L& lds,
+                               const double* g, int row_index) {
+  const Small& sm = I.sm;
+  const int m = I.m, m_i = st.m_i, k = st.k;
+  const float* o = b.out + (size_t)row_index * kOuts;
+  for (int j = threadIdx.x; j < m_i; j += kWG) {
+    lds.c1[j] = sm.gamma[j] + (double)o[j];
+    lds.sslot[j] = (int)((st.iter - m_i + j) % m);
+  }
+  __syncthreads();
+  for (int a = threadIdx.x; a < k; a += kWG) {
+    double acc = 0.0;
+    for (int c = a; c < k; ++c) acc += sm.R[a + (size_t)c * sm.cap] * lds.c1[c];
+    lds.c2[a] = acc;
+  }
+  __syncthreads();
+  const double beta = 1.0 / (1.0 + exp(-(double)o[kWin]));
+  const double omb = 1.0 - beta;
+  for_tiles(I.n, 0, 1, [&](int64_t b2, auto full) {
+    constexpr bool F = decltype(full)::value;
+    double2 gv[kPairs], fv[kPairs], ar[kPairs], aq[kPairs], dummy[kPairs];
+    ld2<F>(gv, g, b2, I.n);
+    ld2<F>(fv, I.f_prev, b2, I.n);
+    zero2(ar);
+    zero2(aq);
+    for (int j = 0; j < m_i; ++j) {
+      double2 d[kPairs];
+      ld2<F>(d, I.ring + (int64_t)lds.sslot[j] * I.ld, b2, I.n);
+      axpy2(ar, d, lds.c1[j]);
+    }
+    combine_cols<F>(I.Q, I.ld, b2, I.n, 0, k, lds.c2, nullptr, aq, dummy);
+#pragma unroll
+    for (int i = 0; i < kPairs; ++i) {
+      gv[i].x = (gv[i].x - ar[i].x) - omb * (fv[i].x - aq[i].x);
+      gv[i].y = (gv[i].y - ar[i].y) - omb * (fv[i].y - aq[i].y);
+    }
+    st2<F>(gv, I.xc, b2, I.n);
+  });
+  __syncthreads();
+  const double ih2 = 1.0 / (I.h * I.h);
+  for (int64_t p = threadIdx.x; p < I.n; p += kWG)
+    I.gc[p] = stencil_point(I.xc, I.f, I.dim, I.s, ih2, I.omega, I.c, p);
+  __syncthreads();
+  return beta;
+}
+
+// ||G(x_c) - x_c||^2; with store_r the residual replaces G(x_c) in I.gc.
+template <class L>
+__device__ double wg_cand_residual(const BInst& I, L& lds, bool store_r) {
+  wg_pass(I.sm, mk_tail(TAIL_NONE, 0), 1, lds, [&](double* acc) {
+    const int lane = threadIdx.x & 63;
+    for_tiles(I.n, 0, 1, [&](int64_t b2, auto full) {
+      constexpr bool F = decltype(full)::value;
+      double2 gc[kPairs], xc[kPairs];
+      ld2<F>(gc, I.gc, b2, I.n);
+      ld2<F>(xc, I.xc, b2, I.n);
+#pragma unroll
+      for (int i = 0; i < kPairs; ++i) gc[i] = make_double2(gc[i].x - xc[i].x, gc[i].y - xc[i].y);
+      if (store_r) st2<F>(gc, I.gc, b2, I.n);
+      const double p = wave_sum(dot2(gc, gc));
+      if (lane == 0) acc[0] += p;
+    });
+  });
+  return lds.red[0];
+}
+
+// Accept the candidate: x <- x_c, G(x) <- G(x_c) (known for the next iteration).
+__device__ void wg_accept(const BInst& I, double* xn) {
+  for_tiles(I.n, 0, 1, [&](int64_t b2, auto full) {
+    constexpr bool F = decltype(full)::value;
+    double2 v[kPairs];
+    ld2<F>(v, I.xc, b2, I.n);
+    st2<F>(v, xn, b2, I.n);
+    ld2<F>(v, I.gc, b2, I.n);
+    st2<F>(v, I.g, b2, I.n);
+  });
+  __syncthreads();
+}
+
+// Training: gradient of L = log(||r||^2 / ||f_i||^2), r = G(x_c) - x_c, with
+// respect to the network outputs.  dL/dx_c = (2 / ||r||^2) J_f^T r with
+// J_f = J - I = -omega (A + 3 c diag(x_c^2)) symmetric; then
+// dL/dgamma' = -G_i^T v + (1 - beta) R^T (Q^T v), dL/dbeta = f_i^T v - w^T (Q^T v).
+template <class L>
+__device__ void wg_train_grad(const BatchArgs& b, const BInst& I, BState& st, L& lds, double beta,
+                              double r2, int row_index) {
+  const Small& sm = I.sm;
+  const int m_i = st.m_i, k = st.k;
+  const double res = st.res_norm;
+  st.loss = log(r2 / (res * res));
+  const double ih2 = 1.0 / (I.h * I.h);
+  const double sc = 2.0 / r2;
+  for (int64_t p = threadIdx.x; p < I.n; p += kWG) {
+    const double xc = I.xc[p], rp = I.gc[p];
+    const double jr = -I.omega * (lap_point(I.gc, I.dim, I.s, ih2, p) + 3.0 * I.c * xc * xc * rp);
+    I.xc[p] = sc * jr;  // v overwrites x_c (each point reads its own x_c first)
+  }
+  __syncthreads();
+  // ring^T v over the m_i slots in use (contiguous 0..m_i-1), Q^T v, f^T v
+  DotsArgs dr{I.ring, I.ld, I.n, I.xc, m_i, nullptr, 0, 0};
+  wg_pass(sm, mk_tail(TAIL_NONE, 0), m_i, lds, [&](double* acc) { dots_body(dr, 0, 1, acc); });
+  for (int j = threadIdx.x; j < m_i; j += kWG) lds.cs[j] = lds.red[j];  // by slot
+  DotsArgs dq{I.Q, I.ld, I.n, I.xc, k, I.f_prev, 0, 0};
+  wg_pass(sm, mk_tail(TAIL_NONE, 0), k, lds, [&](double* acc) { dots_body(dq, 0, 1, acc); });
+  for (int j = threadIdx.x; j < k; j += kWG) lds.sg[j] = lds.red[j];   // Q^T v
+  wg_pass(sm, mk_tail(TAIL_NONE, 0), 1, lds, [&](double* acc) {
+    const int lane = threadIdx.x & 63;
+    for_tiles(I.n, 0, 1, [&](int64_t b2, auto full) {
+      constexpr bool F = decltype(full)::value;
+      double2 fv[kPairs], vv[kPairs];
+      ld2<F>(fv, I.f_prev, b2, I.n);
+      ld2<F>(vv, I.xc, b2, I.n);
+      const double p = wave_sum(dot2(fv, vv));
+      if (lane == 0) acc[0] += p;
+    });
+  });
+  const double fv = lds.red[0];
+  float* drow = b.dout + (size_t)row_index * kOuts;
+  const double omb = 1.0 - beta;
+  for (int j = threadIdx.x; j < kWin; j += kWG) {
+    double d = 0.0;
+    if (j < m_i) {
+      double rtb = 0.0;
+      for (int a = 0; a <= j; ++a) rtb += sm.R[a + (size_t)j * sm.cap] * lds.sg[a];
+      d = -lds.cs[lds.sslot[j]] + omb * rtb;
+    }
+    drow[j] = (float)(d * b.dscale);
+  }
+  if (threadIdx.x == 0) {
+    double wb = 0.0;
+    for (int a = 0; a < k; ++a) wb += lds.c2[a] * lds.sg[a];
+    drow[kWin] = (float)((fv - wb) * beta * (1.0 - beta) * b.dscale);
+  }
+  __syncthreads();
+}
+
+// One unit of work for one instance in the given mode (every thread).
+template <int KB, bool GRAM, class L>
+__device__ BState wg_instance(const BatchArgs& b, const BInst& I, BState st, L& lds, int j) {
+  const double* x = b.ox ? b.ox : I.x;
+  double* xn = b.oxn ? b.oxn : I.x;
+  const double* g = b.og ? b.og : I.g;
+  switch (b.mode) {
+    case BM_PHASE_A: {
+      const bool more = wg_front<KB, GRAM>(b, I, st, lds, x, xn, g);
+      st.pending = more ? 1 : 0;
+      write_features(I, st, b.feat + (size_t)j * kFeat, more);
+      __syncthreads();
+      return st;
+    }
+    case BM_GUARD:
+    case BM_TRAIN: {
+      if (!st.pending) {
+        if (b.mode == BM_TRAIN)
+          for (int t = threadIdx.x; t < kOuts; t += kWG) b.dout[(size_t)j * kOuts + t] = 0.f;
+        __syncthreads();
+        return st;
+      }
+      const double beta = wg_candidate(b, I, st, lds, g, j);
+      st.g_evals += 1;
+      const double r2 = wg_cand_residual(I, lds, b.mode == BM_TRAIN);
+      if (b.mode == BM_GUARD && sqrt(r2) < st.res_norm) {
+        wg_accept(I, xn);
+        st.g_valid = 1;
+        st.accepted += 1;
+      } else {
+        if (b.mode == BM_TRAIN) wg_train_grad(b, I, st, lds, beta, r2, j);
+        wg_plain_update(I, st, lds, x, xn, g);
+      }
+      st.pending = 0;
+      st.iter += 1;
+      return st;
+    }
+    default: {
+      if (wg_front<KB, GRAM>(b, I, st, lds, x, xn, g)) {
+        wg_plain_update(I, st, lds, x, xn, g);
+        st.iter += 1;
+      }
+      return st;
+    }
+  }
 }
 
 template <int KB, bool GRAM>
@@ -273,7 +496,7 @@ __global__ __launch_bounds__(kWG) void k_batch(BatchArgs b) {
     st.iter = b.ov_iter;
     st.k = b.ov_k;
     st.active = 1;
-    const BState out = wg_iteration<KB, GRAM>(b, b.inst[0], st, lds);
+    const BState out = wg_instance<KB, GRAM>(b, b.inst[0], st, lds, 0);
     if (threadIdx.x == 0) b.state[0] = out;
     return;
   }
@@ -285,8 +508,13 @@ __global__ __launch_bounds__(kWG) void k_batch(BatchArgs b) {
     if (idx >= b.count) break;
     const int j = b.order[idx];
     const BState st = b.state[j];
-    if (!st.active) continue;
-    const BState out = wg_iteration<KB, GRAM>(b, b.inst[j], st, lds);
+    if (!st.active && !st.pending) {
+      if (b.mode == BM_PHASE_A) write_features(b.inst[j], st, b.feat + (size_t)j * kFeat, false);
+      if (b.mode == BM_TRAIN)
+        for (int t = threadIdx.x; t < kOuts; t += kWG) b.dout[(size_t)j * kOuts + t] = 0.f;
+      continue;
+    }
+    const BState out = wg_instance<KB, GRAM>(b, b.inst[j], st, lds, j);
     if (threadIdx.x == 0) b.state[j] = out;
     __syncthreads();
   }

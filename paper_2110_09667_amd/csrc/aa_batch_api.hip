@@ -36,6 +36,10 @@ struct aa_batch {
   bool use_graph = true;
   hipGraphExec_t exec = nullptr;
   int exec_iters = 0;
+  bool learned = false;
+  float* d_feat = nullptr;  // [count x AA_MLP_FEATURES]
+  float* d_out = nullptr;   // [count x AA_MLP_OUTPUTS]
+  float* d_dout = nullptr;  // [count x AA_MLP_OUTPUTS]
 };
 
 namespace {
@@ -54,9 +58,9 @@ bool valid_instance(const aa_batch_instance& I) {
   return true;
 }
 
-size_t instance_bytes(int64_t n, int m) {
+size_t instance_bytes(int64_t n, int m, bool learned) {
   const size_t vec = align_up((size_t)ld_of(n) * sizeof(double));
-  size_t b = 4 * vec + 2 * (size_t)m * vec;  // g, f_prev, g_prev, W, Q, ring
+  size_t b = (learned ? 6 : 4) * vec + 2 * (size_t)m * vec;  // g, f_prev, g_prev, W, (xc, gc), Q, ring
   b += 2 * align_up(sizeof(double) * m * m);  // R, T
   b += 3 * align_up(sizeof(double) * m);      // coef0, coef1, gamma
   b += align_up(sizeof(double) * 2 * m);      // Givens
@@ -65,14 +69,17 @@ size_t instance_bytes(int64_t n, int m) {
   return b;
 }
 
-size_t header_bytes(int count) {
-  return align_up(sizeof(BInst) * count) + align_up(sizeof(BState) * count) +
-         align_up(sizeof(int) * count) + align_up(sizeof(unsigned));
+size_t header_bytes(int count, bool learned) {
+  size_t b = align_up(sizeof(BInst) * count) + align_up(sizeof(BState) * count) +
+             align_up(sizeof(int) * count) + align_up(sizeof(unsigned));
+  if (learned)
+    b += align_up(sizeof(float) * count * kFeat) + 2 * align_up(sizeof(float) * count * kOuts);
+  return b;
 }
 
 int bucket(int m) { return m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : 64; }
 
-hipError_t enqueue(aa_batch* b, int iters) {
+hipError_t enqueue_mode(aa_batch* b, int mode, float dscale) {
   BatchArgs a{};
   a.inst = b->d_inst;
   a.state = b->d_state;
@@ -84,6 +91,11 @@ hipError_t enqueue(aa_batch* b, int iters) {
   a.tol = b->tol;
   a.max_iter = b->max_iter;
   a.ov_iter = -1;
+  a.mode = mode;
+  a.feat = b->d_feat;
+  a.out = b->d_out;
+  a.dout = b->d_dout;
+  a.dscale = dscale;
   int grid = b->grid;
   if (grid <= 0) {
     int dev = 0, cus = 256;
@@ -92,10 +104,14 @@ hipError_t enqueue(aa_batch* b, int iters) {
     grid = 2 * cus;
   }
   if (grid > b->count) grid = b->count;
+  hipError_t e = launch_batch_reset(b->d_counter, b->stream);
+  if (e != hipSuccess) return e;
+  return launch_batch(a, grid, b->kbucket, b->gram, b->stream);
+}
+
+hipError_t enqueue(aa_batch* b, int iters) {
   for (int i = 0; i < iters; ++i) {
-    hipError_t e = launch_batch_reset(b->d_counter, b->stream);
-    if (e != hipSuccess) return e;
-    e = launch_batch(a, grid, b->kbucket, b->gram, b->stream);
+    hipError_t e = enqueue_mode(b, BM_PLAIN, 0.f);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -115,10 +131,12 @@ aa_status aa_batch_workspace_size(int count, const aa_batch_instance* inst, int 
                                   unsigned flags, size_t* bytes) {
   (void)flags;
   if (count < 1 || !inst || !bytes || variant < AA_MGS || variant > AA_ICWY) return AA_EINVAL;
-  size_t tot = header_bytes(count);
+  const bool learned = (flags & AA_BATCH_LEARNED) != 0;
+  size_t tot = header_bytes(count, learned);
   for (int j = 0; j < count; ++j) {
     if (!valid_instance(inst[j])) return AA_EINVAL;
-    tot += instance_bytes(inst[j].n, inst[j].m);
+    if (learned && inst[j].m > kWin) return AA_EINVAL;  // features cover a 20-column window
+    tot += instance_bytes(inst[j].n, inst[j].m, learned);
   }
   *bytes = tot;
   return AA_OK;
@@ -149,6 +167,12 @@ aa_status aa_batch_init(aa_batch** out, int count, const aa_batch_instance* inst
   b->d_state = (BState*)(base + o); o = align_up(o + sizeof(BState) * count);
   b->d_order = (int*)(base + o); o = align_up(o + sizeof(int) * count);
   b->d_counter = (unsigned*)(base + o); o = align_up(o + sizeof(unsigned));
+  b->learned = (flags & AA_BATCH_LEARNED) != 0;
+  if (b->learned) {
+    b->d_feat = (float*)(base + o); o = align_up(o + sizeof(float) * count * kFeat);
+    b->d_out = (float*)(base + o); o = align_up(o + sizeof(float) * count * kOuts);
+    b->d_dout = (float*)(base + o); o = align_up(o + sizeof(float) * count * kOuts);
+  }
   std::vector<BInst> hi(count);
   std::vector<BState> hs(count);
   int mmax = 1;
@@ -165,6 +189,10 @@ aa_status aa_batch_init(aa_batch** out, int count, const aa_batch_instance* inst
     I.f_prev = (double*)(base + o); o += vec;
     I.g_prev = (double*)(base + o); o += vec;
     I.W = (double*)(base + o); o += vec;
+    if (b->learned) {
+      I.xc = (double*)(base + o); o += vec;
+      I.gc = (double*)(base + o); o += vec;
+    }
     I.Q = (double*)(base + o); o += vec * m;
     I.ring = (double*)(base + o); o += vec * m;
     Small& sm = I.sm;
@@ -181,6 +209,9 @@ aa_status aa_batch_init(aa_batch** out, int count, const aa_batch_instance* inst
     BState& st = hs[j];
     st.iter = 0; st.conv_iter = -1; st.k = 0; st.m_i = 0; st.active = 1; st.status = 0;
     st.res_norm = st.res0_norm = 0.0;
+    st.g_evals = st.accepted = 0;
+    st.loss = 0.0;
+    st.pending = st.g_valid = 0;
     b->n.push_back(A.n);
     b->m.push_back(m);
     mmax = std::max(mmax, m);
@@ -264,6 +295,49 @@ aa_status aa_batch_read(aa_batch* b, aa_batch_state* states, int* active) {
     for (const BState& st : hs) a += st.active ? 1 : 0;
     *active = a;
   }
+  return AA_OK;
+}
+
+aa_status aa_batch_run_learned(aa_batch* b, aa_mlp* net, int iters) {
+  if (!b || !net || iters < 0 || !b->learned) return AA_EINVAL;
+  if (mlp_stream(net) != b->stream || mlp_max_batch(net) < b->count) return AA_EINVAL;
+  for (int i = 0; i < iters; ++i) {
+    if (enqueue_mode(b, BM_PHASE_A, 0.f) != hipSuccess) return AA_EHIP;
+    aa_status s = aa_mlp_forward(net, b->count, b->d_feat, b->d_out);
+    if (s != AA_OK) return s;
+    if (enqueue_mode(b, BM_GUARD, 0.f) != hipSuccess) return AA_EHIP;
+  }
+  return AA_OK;
+}
+
+aa_status aa_batch_train(aa_batch* b, aa_mlp* net, int iters, float lr) {
+  if (!b || !net || iters < 0 || !b->learned || !(lr >= 0.f)) return AA_EINVAL;
+  if (mlp_stream(net) != b->stream || mlp_max_batch(net) < b->count) return AA_EINVAL;
+  const float dscale = 1.0f / (float)b->count;
+  for (int i = 0; i < iters; ++i) {
+    if (enqueue_mode(b, BM_PHASE_A, 0.f) != hipSuccess) return AA_EHIP;
+    aa_status s = aa_mlp_forward(net, b->count, b->d_feat, b->d_out);
+    if (s != AA_OK) return s;
+    if (enqueue_mode(b, BM_TRAIN, dscale) != hipSuccess) return AA_EHIP;
+    s = aa_mlp_backward(net, b->count, b->d_dout);
+    if (s != AA_OK) return s;
+    s = aa_mlp_adam(net, lr, 0.9f, 0.999f, 1e-8f);
+    if (s != AA_OK) return s;
+  }
+  return AA_OK;
+}
+
+aa_status aa_batch_read_learning(aa_batch* b, float* feat, float* out, float* dout) {
+  if (!b || !b->learned) return AA_EINVAL;
+  const size_t c = (size_t)b->count;
+  if ((feat && hipMemcpyAsync(feat, b->d_feat, sizeof(float) * c * kFeat, hipMemcpyDeviceToHost,
+                              b->stream) != hipSuccess) ||
+      (out && hipMemcpyAsync(out, b->d_out, sizeof(float) * c * kOuts, hipMemcpyDeviceToHost,
+                             b->stream) != hipSuccess) ||
+      (dout && hipMemcpyAsync(dout, b->d_dout, sizeof(float) * c * kOuts, hipMemcpyDeviceToHost,
+                              b->stream) != hipSuccess) ||
+      hipStreamSynchronize(b->stream) != hipSuccess)
+    return AA_EHIP;
   return AA_OK;
 }
 

@@ -137,6 +137,7 @@ struct BInst {
   double* x;              // iterate (updated in place)
   double* g;              // G(x) buffer (dim > 0) or the caller's G(x)
   double* f_prev; double* g_prev; double* W; double* Q; double* ring;
+  double* xc; double* gc; // learned step: candidate and G(candidate) / adjoint work
   Small sm;               // R, T, coefficients, gamma, Givens, scalars, status
 };
 
@@ -146,7 +147,21 @@ struct BState {
   int64_t conv_iter;      // iteration at which the instance stopped (-1: running)
   int k, m_i, active, status;
   double res_norm, res0_norm;
+  int64_t g_evals, accepted;
+  double loss;
+  int pending, g_valid;
 };
+
+// Modes of the batched kernel.
+enum BatchMode : int {
+  BM_PLAIN = 0,   // a whole AA iteration
+  BM_PHASE_A = 1, // up to R gamma = Q^T f_i, then the network features
+  BM_GUARD = 2,   // learned candidate, guard, accept or plain step
+  BM_TRAIN = 3    // plain step + loss gradient w.r.t. the network outputs
+};
+constexpr int kFeat = AA_MLP_FEATURES;   // network inputs per instance
+constexpr int kOuts = AA_MLP_OUTPUTS;    // network outputs per instance
+constexpr int kWin = kOuts - 1;          // window the features are padded to
 static_assert(sizeof(BState) == sizeof(aa_batch_state), "BState mirrors aa_batch_state");
 
 struct BatchArgs {
@@ -158,9 +173,16 @@ struct BatchArgs {
   // caller's x, G(x), x_next and the host's iteration index and column count
   const double* ox; const double* og; double* oxn;
   int64_t ov_iter; int ov_k;
+  int mode;               // BatchMode
+  float* feat;            // [count x kFeat] network inputs (phase A)
+  const float* out;       // [count x kOuts] network outputs (guard / train)
+  float* dout;            // [count x kOuts] loss gradient (train)
+  float dscale;           // scale of dout (1 / count)
 };
 
 hipError_t launch_batch(const BatchArgs&, int grid, int kbucket, bool gram, hipStream_t);
+hipStream_t mlp_stream(const aa_mlp*);
+int mlp_max_batch(const aa_mlp*);
 hipError_t launch_batch_reset(unsigned* counter, hipStream_t);
 hipError_t launch_batch_init(BInst* inst, int count, hipStream_t);
 

@@ -266,6 +266,11 @@ static aa_status mlp_reset_state(aa_mlp* n) {
   return hipGetLastError() == hipSuccess ? AA_OK : AA_EHIP;
 }
 
+namespace aa {
+hipStream_t mlp_stream(const aa_mlp* n) { return n->stream; }
+int mlp_max_batch(const aa_mlp* n) { return n->max_batch; }
+}  // namespace aa
+
 extern "C" {
 
 aa_status aa_mlp_workspace_size(int max_batch, size_t* bytes) {

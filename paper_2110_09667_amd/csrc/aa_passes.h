@@ -84,9 +84,11 @@ __device__ inline void run_tail(const Small& sm, const Tail& t, const double* re
       }
       break;
     case TAIL_RHS:
-      // Alg. 2, last line: back substitution R gamma = c, c = Q^T f_i.
+      // Alg. 2, last line: back substitution R gamma = c, c = Q^T f_i (c is
+      // kept in coef1, free after QRAdd, for the learned step's features).
       if (tid < 64) {
         double x = (lane < k) ? red[lane] : 0.0;
+        if (lane < k) sm.coef1[lane] = x;
         double gam = 0.0;
         for (int a = k - 1; a >= 0; --a) {
           const double ga = __shfl(x, a, 64) / R[a + (size_t)a * cap];
@@ -522,6 +524,28 @@ __device__ inline void gram_store(const v4d (&acc)[GramShape<KMAX>::NBP], double
 // ---------------------------------------------------------------------------
 // elementwise passes
 // ---------------------------------------------------------------------------
+
+// (A u)_p, A the (2 dim + 1)-point Dirichlet Laplacian on an s^dim grid
+// (x fastest) scaled by ih2 = 1/h^2.
+__device__ __forceinline__ double lap_point(const double* __restrict__ u, int dim, int64_t s,
+                                            double ih2, int64_t p) {
+  const int64_t ix = p % s;
+  const double up = u[p];
+  double nb = 0.0;
+  if (ix > 0) nb += u[p - 1];
+  if (ix < s - 1) nb += u[p + 1];
+  if (dim >= 2) {
+    const int64_t iy = (p / s) % s;
+    if (iy > 0) nb += u[p - s];
+    if (iy < s - 1) nb += u[p + s];
+  }
+  if (dim >= 3) {
+    const int64_t s2 = s * s, iz = p / s2;
+    if (iz > 0) nb += u[p - s2];
+    if (iz < s - 1) nb += u[p + s2];
+  }
+  return (2.0 * dim * up - nb) * ih2;
+}
 
 // G(u)_p = u_p - omega ((A u)_p + c u_p^3 - f_p), A the (2 dim + 1)-point
 // Dirichlet Laplacian on an s^dim grid (x fastest) scaled by ih2 = 1/h^2.
