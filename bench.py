@@ -38,14 +38,14 @@ VARIANTS = ["mgs", "cgs2", "dcgs2", "icwy"]
 PROFILE_JSON = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
-def run_variant(prob, m, variant, steps, warmup, grid=None, profile=True):
+def run_variant(prob, m, variant, steps, warmup, grid=None, profile=True, flags=0):
     import torch
     from paper_2110_09667_amd import aa
 
     n = prob.n
     dev = torch.device("cuda:0")
     f_d = device_rhs(prob)
-    ctx = aa.AAContext(n, m, variant)
+    ctx = aa.AAContext(n, m, variant, flags)
     if grid:
         ctx.set_grid(*grid)
     x = torch.zeros(n, dtype=torch.float64, device=dev)
@@ -58,11 +58,9 @@ def run_variant(prob, m, variant, steps, warmup, grid=None, profile=True):
     for _ in range(m + 1 + warmup):
         step()
     torch.cuda.synchronize(dev)
-    if profile:
-        ctx.profile(True)
+    # timed steps, unprofiled (the step time reported)
     stream = torch.cuda.current_stream(dev)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(steps):
@@ -71,7 +69,15 @@ def run_variant(prob, m, variant, steps, warmup, grid=None, profile=True):
     torch.cuda.synchronize(dev)
     wall = time.perf_counter() - t0
     ms_total = e0.elapsed_time(e1)
-    prof = ctx.profile_read() if profile else {}
+    # the same number of steps again with per-launch events (kernel breakdown)
+    prof = {}
+    if profile:
+        ctx.profile(True)
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize(dev)
+        prof = ctx.profile_read()
+        ctx.profile(False)
     info = ctx.info()
     if info.status != 0:
         raise RuntimeError(f"{variant}: device status {info.status}")
@@ -79,6 +85,7 @@ def run_variant(prob, m, variant, steps, warmup, grid=None, profile=True):
     bytes_per_step = (sum(b for (_, _, b) in prof.values()) / steps + 3 * u_bytes) if prof else None
     out = {
         "variant": variant,
+        "steps": steps,
         "ms_per_step": ms_total / steps,
         "wall_ms_per_step": 1e3 * wall / steps,
         "bytes_per_step": bytes_per_step,
@@ -93,6 +100,253 @@ def run_variant(prob, m, variant, steps, warmup, grid=None, profile=True):
     del x, g, f_d
     torch.cuda.empty_cache()
     return out
+
+
+def qr_micro(n, ks, variant, reps=3):
+    """QRAdd / QRDelete on their own (the standalone microbenchmark): a basis
+    of k orthonormal columns (seeded Gaussian columns added one by one), then
+    ``reps`` cycles of [QRAdd of a Gaussian v; QRDelete], which keeps k fixed.
+    Each call is timed with events on the context's stream; its algorithmic
+    bytes come from the library's per-launch accounting.  Returns
+    {k: {"add_us", "add_gbs", "delete_us", "delete_gbs"}} (medians)."""
+    import torch
+    from paper_2110_09667_amd import aa
+    import aa_workloads as W
+
+    dev = torch.device("cuda:0")
+    kmax = max(ks)
+    ctx = aa.AAContext(n, kmax + 1, variant, flags=aa.QR_ONLY)
+    col = torch.empty(n, dtype=torch.float64, device=dev)
+    v = torch.empty(n, dtype=torch.float64, device=dev)
+    aa.aa_fill_normal(v, W.SEED_QR_V, 0)
+    stream = torch.cuda.current_stream(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ctx.profile(True)
+    out = {}
+    j = 0
+    for k in sorted(ks):
+        while ctx.info().k < k:
+            aa.aa_fill_normal(col, W.SEED_QR_Q, j)
+            ctx.qr_add(col)
+            j += 1
+        adds, dels = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize(dev)
+            aa.aa_profile_reset(ctx.ctx)
+            ev[0].record(stream)
+            ctx.qr_add(v)
+            ev[1].record(stream)
+            torch.cuda.synchronize(dev)
+            b_add = sum(b for (_, _, b) in ctx.profile_read().values())
+            aa.aa_profile_reset(ctx.ctx)
+            ev[1].record(stream)
+            ctx.qr_delete()
+            ev[2].record(stream)
+            torch.cuda.synchronize(dev)
+            b_del = sum(b for (_, _, b) in ctx.profile_read().values())
+            adds.append((ev[0].elapsed_time(ev[1]), b_add))
+            dels.append((ev[1].elapsed_time(ev[2]), b_del))
+        if ctx.info().status != 0:
+            raise RuntimeError(f"qr_micro {variant} k={k}: status {ctx.info().status}")
+        (ta, ba), (td, bd) = sorted(adds)[reps // 2], sorted(dels)[reps // 2]
+        out[k] = {"add_us": 1e3 * ta, "add_gbs": ba / ta / 1e6,
+                  "delete_us": 1e3 * td, "delete_gbs": (bd / td / 1e6) if td > 0 else None}
+    ctx.close()
+    del col, v
+    torch.cuda.empty_cache()
+    return out
+
+
+class BatchProblem2D:
+    """One instance of the batched 2D workload, f generated on the GPU by the
+    library's generator (bit-identical to aa_workloads.batch_problem)."""
+
+    def __init__(self, inst):
+        import torch
+        import aa_workloads as W
+        from paper_2110_09667_amd import aa
+        self.d, self.s, self.c = 2, inst.s, inst.c
+        self.n = inst.n
+        self.h = 1.0 / (inst.s + 1)
+        self.omega = 0.9 / W.laplacian_lambda_max(2, inst.s)
+        self.f = torch.empty(self.n, dtype=torch.float64, device="cuda:0")
+        aa.aa_fill_uniform(self.f, inst.seed, 1)
+
+
+def batch_iter_vectors(variant, m, m_i, k_before):
+    """Algorithmic n-vectors of one batched iteration of one instance (the
+    same byte model as the single-instance path, G included)."""
+    k = k_before
+    add = {"mgs": 4 * k + 3 if k else 3, "cgs2": 3 * k + 6, "dcgs2": 2 * k + (6 if k >= 3 else 5),
+           "icwy": 2 * k + 5}[variant]
+    delete = (2 * m - 1) if m_i == m else 0
+    return 3 + 8 + delete + add + (m_i + 1) + (m_i + 3)
+
+
+def batched_run(probs, ms, variant, tol, cap, chunk, stream, net=None, steady=20, tune=True):
+    """Drive a batch to tolerance (or the iteration cap): returns the time of
+    the first 21 iterations (every window full after them), the schedule the
+    autotuner picked (plain batches), the steady per-iteration time, the wall
+    time until no instance is active and the final states."""
+    import torch
+    from paper_2110_09667_amd import aa
+    flags = aa.BATCH_LEARNED if net is not None else 0
+    b = aa.AABatch(probs, ms, variant, flags=flags, tol=tol, max_iter=cap, stream=stream)
+
+    def run(k):
+        if net is None:
+            b.run(k)
+        else:
+            b.run_learned(net, k)
+
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e[0].record(stream)
+    run(21)
+    e[1].record(stream)
+    it = 21
+    sched = None
+    if tune and net is None:
+        # the schedule autotuner times real iterations under each candidate
+        sched = b.autotune(3)
+        it += 3 * sched.trials
+    e[2].record(stream)
+    run(steady)
+    e[3].record(stream)
+    it += steady
+    while True:
+        st, active = b.read()
+        if active == 0 or it >= cap:
+            break
+        run(chunk)
+        it += chunk
+    wall = time.perf_counter() - t0
+    out = {"fill_ms": e[0].elapsed_time(e[1]), "steady_ms_per_iter": e[2].elapsed_time(e[3]) / steady,
+           "wall_s": wall, "states": st, "iters_run": it,
+           "schedule": ({"grid": sched.grid, "order": ["largest n*m first", "as given"][sched.order],
+                         "ms_per_iter": round(sched.ms_per_iter, 3), "trials": sched.trials}
+                        if sched else None)}
+    b.close()
+    del b
+    return out
+
+
+def one_at_a_time(probs, ms, variant, tol, cap, check_every=10):
+    """The same instances solved one after another through the single-instance
+    entry points (aa_problem_apply + aa_step on one context per instance),
+    each until ||f_i|| <= tol ||f_0|| (tested every ``check_every`` steps) or
+    ``cap`` iterations.  Returns (seconds, iterations, converged) per instance."""
+    import torch
+    from paper_2110_09667_amd import aa
+    out = []
+    for p, m in zip(probs, ms):
+        ctx = aa.AAContext(p.n, m, variant)
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda:0")
+        g = torch.empty_like(x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, conv = 0, False
+        while it < cap:
+            for _ in range(check_every):
+                aa.aa_problem_apply(p.d, p.s, p.h, p.omega, p.c, p.f, x, g)
+                ctx.step(x, g, x)
+                it += 1
+            info = ctx.info()
+            if info.iter > 1 and info.res_norm <= tol * info.res0_norm:
+                conv = True
+                break
+        torch.cuda.synchronize()
+        out.append((time.perf_counter() - t0, it, conv))
+        ctx.close()
+        del x, g
+    return out
+
+
+def batched_suite(variant, count, cap, train_count, train_iters, sample, lr=1e-3):
+    """Batched AA on the 2D workload table (instance seeds 0..count-1):
+    plain batched to tol 1e-8 (or the cap), the learned-guarded batch with a
+    network trained on instances of disjoint seeds, and a seeded sample of
+    the same instances run one at a time through the single-instance path."""
+    import numpy as np
+    import torch
+    import aa_workloads as W
+    from paper_2110_09667_amd import aa
+
+    tol = 1e-8
+    insts = W.batch_table(count)
+    probs = [BatchProblem2D(i) for i in insts]
+    ms = [i.m for i in insts]
+    sum_n = sum(p.n for p in probs)
+    stream = torch.cuda.Stream()
+    res = {"instances": count, "sum_n": sum_n, "variant": variant, "tol": tol,
+           "max_iter": cap}
+    with torch.cuda.stream(stream):
+        # algorithmic bytes of one full-window iteration of every instance
+        vec = sum(batch_iter_vectors(variant, i.m, i.m, i.m - 1) * p.n for i, p in zip(insts, probs))
+        plain = batched_run(probs, ms, variant, tol, cap, 50, stream)
+        print(f"# batched plain: {plain['steady_ms_per_iter']:.2f} ms/iter, "
+              f"{plain['wall_s']:.1f} s", file=sys.stderr, flush=True)
+        # training on disjoint seeds: plain-AA trajectories, one Adam step per
+        # iteration over the whole training batch
+        tinsts = W.batch_table(train_count, first_seed=W.SEED_TRAIN_BASE)
+        tprobs = [BatchProblem2D(i) for i in tinsts]
+        net = aa.AAMlp(max(count, train_count), seed=1, stream=stream)
+        tb = aa.AABatch(tprobs, [i.m for i in tinsts], variant, flags=aa.BATCH_LEARNED,
+                        tol=0.0, max_iter=10**9, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tb.train(net, train_iters, lr)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        tstates, _ = tb.read()
+        tb.close()
+        del tb, tprobs
+        torch.cuda.empty_cache()
+        learned = batched_run(probs, ms, variant, tol, cap, 50, stream, net=net)
+        print(f"# batched learned: {learned['steady_ms_per_iter']:.2f} ms/iter, "
+              f"{learned['wall_s']:.1f} s", file=sys.stderr, flush=True)
+    rng = np.random.default_rng(12345)
+    pick = sorted(rng.choice(count, size=min(sample, count), replace=False).tolist())
+    single = one_at_a_time([probs[j] for j in pick], [ms[j] for j in pick], variant, tol, cap)
+    print(f"# one at a time ({len(pick)} sampled): {sum(t for t, _, _ in single):.1f} s",
+          file=sys.stderr, flush=True)
+
+    def summary(run):
+        st = run["states"]
+        conv = [s for s in st if s.res_norm <= tol * s.res0_norm]
+        its = np.array([s.stop_iter for s in conv]) if conv else np.array([0])
+        return {"wall_s": round(run["wall_s"], 3),
+                "steady_ms_per_iter": round(run["steady_ms_per_iter"], 3),
+                "converged": len(conv),
+                "median_iters_converged": float(np.median(its)),
+                "g_evals_total": int(sum(s.g_evals for s in st)),
+                "accepted_total": int(sum(s.accepted for s in st))}
+
+    sp, sl = summary(plain), summary(learned)
+    both = [j for j in range(count)
+            if plain["states"][j].res_norm <= tol * plain["states"][j].res0_norm
+            and learned["states"][j].res_norm <= tol * learned["states"][j].res0_norm]
+    gi = np.array([learned["states"][j].stop_iter / plain["states"][j].stop_iter for j in both]) \
+        if both else np.array([np.nan])
+    t_single = sum(t for t, _, _ in single)
+    res.update({
+        "plain": {**sp, "schedule": plain["schedule"],
+                  "inst_iters_per_s": round(count / (plain["steady_ms_per_iter"] * 1e-3)),
+                  "algorithmic_gbs": round(8.0 * vec / (plain["steady_ms_per_iter"] * 1e-3) / 1e9, 1)},
+        "learned": {**sl, "train_instances": train_count, "train_iters": train_iters,
+                    "train_samples": train_count * max(0, train_iters - 1), "train_s": round(train_s, 2),
+                    "train_final_mean_loss": float(np.mean([s.loss for s in tstates])),
+                    "both_converged": len(both),
+                    "median_iter_ratio_learned_over_plain": float(np.median(gi))},
+        "one_at_a_time_sample": {
+            "instances": len(pick), "seconds": round(t_single, 3),
+            "converged": sum(1 for _, _, c in single if c),
+            "iterations": int(sum(i for _, i, _ in single)),
+            "estimated_seconds_all": round(t_single * count / len(pick), 1),
+            "stop_test_every": 10},
+    })
+    return res
 
 
 def device_rhs(prob):
@@ -183,6 +437,20 @@ def main():
     ap.add_argument("--no-other-variants", action="store_true")
     ap.add_argument("--grid", type=int, nargs=2, default=None,
                     help="max workgroups: streaming passes, Gram pass")
+    ap.add_argument("--no-qr-micro", action="store_true",
+                    help="skip the standalone QRAdd/QRDelete measurements")
+    ap.add_argument("--rhs", choices=["separate", "fused"], default="separate",
+                    help="R gamma = Q^T f_i as its own pass (as Alg. 2 writes it) or folded "
+                         "into the QRAdd passes (AA_FUSE_RHS)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched / learned-guarded / one-at-a-time comparison")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--batch-cap", type=int, default=1000,
+                    help="iteration cap of the batched time-to-tolerance runs")
+    ap.add_argument("--train-count", type=int, default=4096)
+    ap.add_argument("--train-iters", type=int, default=50)
+    ap.add_argument("--single-sample", type=int, default=64,
+                    help="instances run one at a time for the comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (5 times), to "
                          "calibrate the HBM byte counters of a profiler")
@@ -218,7 +486,9 @@ def main():
     prob = Problem3D(args.s)
     print(f"# workload: 3D nonlinear, s={args.s}, n={prob.n}, m={args.m}", file=sys.stderr,
           flush=True)
-    main_res = run_variant(prob, args.m, args.variant, args.steps, args.warmup, args.grid)
+    flags = aa.FUSE_RHS if args.rhs == "fused" else 0
+    main_res = run_variant(prob, args.m, args.variant, args.steps, args.warmup, args.grid,
+                           flags=flags)
     print(f"# {args.variant}: {main_res['ms_per_step']:.3f} ms/step, "
           f"{main_res['gbs']:.0f} GB/s", file=sys.stderr, flush=True)
     others = {}
@@ -226,13 +496,39 @@ def main():
         for v in VARIANTS:
             if v == args.variant:
                 continue
-            r = run_variant(prob, args.m, v, max(5, args.steps // 2), 2, args.grid)
+            r = run_variant(prob, args.m, v, max(5, args.steps // 2), 2, args.grid, flags=flags)
             others[v] = r
             print(f"# {v}: {r['ms_per_step']:.3f} ms/step, {r['gbs']:.0f} GB/s",
                   file=sys.stderr, flush=True)
 
+    qradd = {}
+    if not args.no_qr_micro:
+        # QRAdd / QRDelete alone: at the 3D workload's n with k = m - 1 (the
+        # add that follows a delete in a full window, m = 5, 10, 20, 50), and
+        # at n = 2^26 for k = 1..64
+        for label, n_q, ks in (("n=%d" % prob.n, prob.n, [4, 9, 19, 49]),
+                               ("n=%d" % (1 << 26), 1 << 26, [1, 2, 4, 8, 16, 32, 64])):
+            qradd[label] = {}
+            for v in VARIANTS:
+                # the ICWY window holds at most 64 columns: its largest add is k = 63
+                r = qr_micro(n_q, [min(k, 63) if v == "icwy" else k for k in ks], v)
+                qradd[label][v] = {f"k={k}": {"add_us": round(d["add_us"], 1),
+                                              "add_gbs": round(d["add_gbs"], 1),
+                                              "add_pct_hbm": round(100 * d["add_gbs"] / HBM_PEAK_GBS, 1),
+                                              "delete_us": round(d["delete_us"], 1),
+                                              "delete_gbs": (round(d["delete_gbs"], 1)
+                                                             if d["delete_gbs"] else None)}
+                                   for k, d in r.items()}
+                print(f"# qradd {label} {v}: " + ", ".join(
+                    f"k={k} {d['add_gbs']:.0f}" for k, d in r.items()), file=sys.stderr, flush=True)
+
+    batched = None
+    if not args.no_batch:
+        batched = batched_suite(args.variant, args.batch_count, args.batch_cap, args.train_count,
+                                args.train_iters, args.single_sample)
+
     kern = main_res["kernels"]
-    dom = max(kern, key=lambda k: kern[k]["ms"])
+    dom = max((k for k in kern if kern[k]["bytes"] > 0), key=lambda k: kern[k]["ms"])
     achieved = kern[dom]["gbs"]
     traffic = load_traffic(dom, args.variant, args.m)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -262,14 +558,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"AA recycle iteration, 3D nonlinear {args.s}^3 "
                                f"(n={prob.n}), m={args.m}",
-                   "variant": args.variant, "n": prob.n, "m": args.m,
+                   "variant": args.variant, "n": prob.n, "m": args.m, "rhs": args.rhs,
                    "parallelism": "single GPU"},
         "pct_hbm_peak": 100.0 * main_res["gbs"] / HBM_PEAK_GBS,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "qradd": qradd,
+        "batched": batched,
         "per_variant": {v: {"ms_per_step": r["ms_per_step"], "gbs": r["gbs"],
                             "pct_hbm_peak": 100.0 * r["gbs"] / HBM_PEAK_GBS,
-                            "kernels": {k: round(d["gbs"], 1) if d["gbs"] else None
+                            "kernels": {k: {"gbs": round(d["gbs"], 1) if d["gbs"] else None,
+                                            "us_per_step": round(1e3 * d["ms"] / r["steps"], 1)}
                                         for k, d in r["kernels"].items()}}
                         for v, r in per_variant.items()},
     }

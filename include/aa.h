@@ -65,6 +65,14 @@ enum {
   /* Alg. 6: reorthogonalize the previous column when m_i >= 3 instead of the
    * printed m_i > 3. */
   AA_DCGS2_GUARD_GE3 = 1u << 4,
+  /* aa_step with CGS-2, DCGS-2 or ICWY: form c = Q^T f_i inside the QRAdd
+   * passes (Q^T f with the first pass's block dot products, c_k = w^T f /
+   * R_kk with the norm of the new column) and solve R gamma = c in the last
+   * pass's tail, instead of a separate pass over Q after QRAdd (Alg. 2, last
+   * line).  Same c, different rounding order; saves one pass over Q and one
+   * reduction per iteration.  MGS and the first QRAdd keep the separate
+   * pass. */
+  AA_FUSE_RHS = 1u << 3,
   /* Workspace for the QR update only (aa_qr_add / aa_qr_delete /
    * aa_qr_solve); aa_step is then unavailable.  Saves (m + 3) n doubles. */
   AA_QR_ONLY = 1u << 8
@@ -158,13 +166,17 @@ typedef enum {
   AA_K_HISTORY = 6, /* f_i, Delta f, Delta g                              */
   AA_K_XUPDATE = 7, /* x_{i+1} = G(x_i) - sum gamma_j Delta g_j           */
   AA_K_FUSED = 8,   /* whole iteration in one workgroup (small n)         */
-  AA_K_COUNT = 9
+  AA_K_FINALIZE = 9, /* one-workgroup reduction + dense tail after a pass  */
+  AA_K_COUNT = 10
 } aa_kernel_kind;
 
-/* Enable (1) or disable (0) per-launch timing: every kernel the context
- * enqueues is bracketed by two hipEvents on the context's stream (events are
- * created on the first enable; no device memory is allocated).  Disabling or
- * aa_profile_reset discards what was recorded. */
+/* Enable (1) or disable (0) per-launch timing: every pass the context
+ * enqueues is bracketed by hipEvents on the context's stream, with one more
+ * event between a streaming pass and its finalize kernel, so the pass and the
+ * finalize are timed apart (events are created on the first enable; no device
+ * memory is allocated).  Event records order the stream more strictly than
+ * plain launches, so profiled steps run slightly slower than unprofiled
+ * ones.  Disabling or aa_profile_reset discards what was recorded. */
 aa_status aa_profile_enable(aa_ctx *ctx, int enable);
 
 /* Totals for one kernel kind since the last reset: elapsed milliseconds
@@ -246,6 +258,29 @@ aa_status aa_batch_read(aa_batch *b, aa_batch_state *h_states, int *h_active);
  * (0 = 2 per compute unit), instance order (0 = largest n*m first,
  * 1 = as given), graph replay on/off. */
 aa_status aa_batch_set_schedule(aa_batch *b, int grid, int order, int use_graph);
+
+typedef struct {
+  int grid;          /* persistent workgroups chosen                         */
+  int order;         /* instance order chosen (as aa_batch_set_schedule)     */
+  double ms_per_iter;/* its measured time per batched iteration              */
+  int trials;        /* candidate schedules timed (0: taken from the cache)  */
+} aa_batch_schedule;
+
+/* Schedule autotuner (the batched path's tuning step; not in the paper).
+ * Times `iters` real iterations of the batch under each candidate schedule
+ * -- persistent workgroups in {1, 2, 3, 4} per compute unit (capped at the
+ * instance count) x instance order {largest n*m first, as given} -- with
+ * events on the batch's stream, and keeps the fastest (graph replay stays as
+ * set).  The iterations it runs are ordinary progress of the batch, so call
+ * it once the windows are full (after max m iterations) for a fair
+ * comparison.  With cache_path non-NULL the result is looked up first in,
+ * and afterwards appended to, a text file of lines
+ * "<gcn arch> <workload signature> <grid> <order> <ms per iteration>"; the
+ * signature hashes the variant, the flags and every instance's (n, m, dim).
+ * A cache hit applies the stored schedule and runs nothing.  best may be
+ * NULL.  Waits for the stream. */
+aa_status aa_batch_autotune(aa_batch *b, int iters, const char *cache_path,
+                            aa_batch_schedule *best);
 
 /* Learned-guarded iterations (not part of the paper): after R gamma = Q^T f_i
  * the network proposes delta gamma and beta from R and Q^T f_i; the candidate

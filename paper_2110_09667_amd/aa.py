@@ -17,6 +17,7 @@ MGS, CGS2, DCGS2, ICWY = 0, 1, 2, 3
 VARIANTS = {"mgs": MGS, "cgs2": CGS2, "dcgs2": DCGS2, "icwy": ICWY}
 DCGS2_LITERAL = 1 << 1
 DCGS2_GUARD_GE3 = 1 << 4
+FUSE_RHS = 1 << 3
 QR_ONLY = 1 << 8
 MAX_COLS = 65
 
@@ -30,7 +31,7 @@ SYMBOLS = [
     "aa_fill_uniform", "aa_fill_normal", "aa_version", "aa_profile_enable",
     "aa_profile_read", "aa_profile_reset", "aa_set_grid", "aa_set_fused_threshold",
     "aa_batch_workspace_size", "aa_batch_init", "aa_batch_run", "aa_batch_read",
-    "aa_batch_set_schedule", "aa_batch_destroy", "aa_mlp_param_count",
+    "aa_batch_set_schedule", "aa_batch_autotune", "aa_batch_destroy", "aa_mlp_param_count",
     "aa_mlp_workspace_size", "aa_mlp_init", "aa_mlp_reseed", "aa_mlp_set_params",
     "aa_mlp_get_params", "aa_mlp_get_grads", "aa_mlp_forward", "aa_mlp_backward",
     "aa_mlp_adam", "aa_mlp_destroy", "aa_batch_run_learned", "aa_batch_train",
@@ -40,7 +41,7 @@ SYMBOLS = [
 BATCH_LEARNED = 1 << 9
 
 KERNEL_KINDS = ["dots", "update", "cgs2b", "givens", "rotate", "scale", "history", "xupdate",
-                "fused"]
+                "fused", "finalize"]
 
 
 class AAError(RuntimeError):
@@ -59,6 +60,11 @@ class BatchInstance(C.Structure):
     _fields_ = [("n", C.c_int64), ("m", C.c_int), ("dim", C.c_int), ("s", C.c_int64),
                 ("h", C.c_double), ("omega", C.c_double), ("c", C.c_double),
                 ("d_f", C.c_void_p), ("d_x", C.c_void_p)]
+
+
+class BatchSchedule(C.Structure):
+    _fields_ = [("grid", C.c_int), ("order", C.c_int), ("ms_per_iter", C.c_double),
+                ("trials", C.c_int)]
 
 
 class BatchState(C.Structure):
@@ -111,6 +117,7 @@ def lib():
         "aa_batch_run": [P, I],
         "aa_batch_read": [P, C.POINTER(BatchState), C.POINTER(I)],
         "aa_batch_set_schedule": [P, I, I, I],
+        "aa_batch_autotune": [P, I, C.c_char_p, C.POINTER(BatchSchedule)],
         "aa_batch_destroy": [P],
         "aa_mlp_workspace_size": [I, C.POINTER(C.c_size_t)],
         "aa_mlp_init": [C.POINTER(P), I, U64, P, C.c_size_t, P],
@@ -417,6 +424,15 @@ class AABatch:
 
     def set_schedule(self, grid: int = 0, order: int = 0, use_graph: bool = True):
         aa_batch_set_schedule(self.b, grid, order, use_graph)
+
+    def autotune(self, iters: int = 3, cache_path: str | None = None) -> "BatchSchedule":
+        """Pick the persistent grid and instance order by timing real
+        iterations (see aa_batch_autotune); returns the chosen schedule."""
+        best = BatchSchedule()
+        _check(lib().aa_batch_autotune(self.b, iters,
+                                       cache_path.encode() if cache_path else None,
+                                       C.byref(best)), "aa_batch_autotune")
+        return best
 
     def run_learned(self, net, iters: int):
         _check(lib().aa_batch_run_learned(self.b, net.net, iters), "aa_batch_run_learned")

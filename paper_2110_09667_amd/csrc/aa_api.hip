@@ -37,8 +37,9 @@ struct aa_ctx {
   int64_t fused_max = 16384;
   // per-launch timing (aa_profile_enable)
   bool prof_on = false;
-  std::vector<hipEvent_t> ev;   // pairs: 2 p (start), 2 p + 1 (stop)
+  std::vector<hipEvent_t> ev;   // per launch p: 3p start, 3p+1 pass end, 3p+2 stop
   std::vector<int> ev_kind;
+  std::vector<char> ev_mid;
   int ev_used = 0;
   double prof_ms[AA_K_COUNT] = {};
   int64_t prof_launches[AA_K_COUNT] = {};
@@ -116,20 +117,30 @@ constexpr int kEventPairs = 4096;
 
 hipError_t prof_drain(aa_ctx* c) {
   if (c->ev_used == 0) return hipSuccess;
-  hipError_t e = hipEventSynchronize(c->ev[2 * (c->ev_used - 1) + 1]);
+  hipError_t e = hipEventSynchronize(c->ev[3 * (c->ev_used - 1) + 2]);
   if (e != hipSuccess) return e;
   for (int p = 0; p < c->ev_used; ++p) {
     float ms = 0.f;
-    e = hipEventElapsedTime(&ms, c->ev[2 * p], c->ev[2 * p + 1]);
-    if (e != hipSuccess) return e;
-    c->prof_ms[c->ev_kind[p]] += ms;
+    if (c->ev_mid[p]) {
+      e = hipEventElapsedTime(&ms, c->ev[3 * p], c->ev[3 * p + 1]);
+      if (e != hipSuccess) return e;
+      c->prof_ms[c->ev_kind[p]] += ms;
+      e = hipEventElapsedTime(&ms, c->ev[3 * p + 1], c->ev[3 * p + 2]);
+      if (e != hipSuccess) return e;
+      c->prof_ms[AA_K_FINALIZE] += ms;
+    } else {
+      e = hipEventElapsedTime(&ms, c->ev[3 * p], c->ev[3 * p + 2]);
+      if (e != hipSuccess) return e;
+      c->prof_ms[c->ev_kind[p]] += ms;
+    }
   }
   c->ev_used = 0;
   return hipSuccess;
 }
 
-// Enqueue one kernel; with profiling on, bracket it with an event pair and
-// account `vecs` algorithmic vector transfers (8 n bytes each) to its kind.
+// Enqueue one pass; with profiling on, bracket it with events (plus one
+// between the pass kernel and its finalize kernel, if it has one) and account
+// `vecs` algorithmic vector transfers (8 n bytes each) to its kind.
 template <class F>
 hipError_t timed(aa_ctx* c, int kind, double vecs, F&& launch) {
   if (!c->prof_on) return launch();
@@ -138,16 +149,21 @@ hipError_t timed(aa_ctx* c, int kind, double vecs, F&& launch) {
     if (e != hipSuccess) return e;
   }
   const int p = c->ev_used;
-  hipError_t e = hipEventRecord(c->ev[2 * p], c->stream);
+  hipError_t e = hipEventRecord(c->ev[3 * p], c->stream);
   if (e != hipSuccess) return e;
+  set_profile_mid(c->ev[3 * p + 1]);
   e = launch();
+  const bool mid = profile_mid_used();
+  set_profile_mid(nullptr);
   if (e != hipSuccess) return e;
-  e = hipEventRecord(c->ev[2 * p + 1], c->stream);
+  e = hipEventRecord(c->ev[3 * p + 2], c->stream);
   if (e != hipSuccess) return e;
   c->ev_kind[p] = kind;
+  c->ev_mid[p] = mid ? 1 : 0;
   c->ev_used = p + 1;
   c->prof_launches[kind] += 1;
   c->prof_bytes[kind] += vecs * 8.0 * (double)c->n;
+  if (mid) c->prof_launches[AA_K_FINALIZE] += 1;
   return hipSuccess;
 }
 
@@ -158,10 +174,18 @@ Tail tail(int op, int k) {
   return t;
 }
 
-// QRAdd of d_v as column k (Algs. 3-6); d_v is read-only.
-aa_status qr_add_impl(aa_ctx* c, const double* v) {
+// QRAdd of d_v as column k (Algs. 3-6); d_v is read-only.  With f non-null
+// (AA_FUSE_RHS, k >= 1, not MGS) the passes also form c = Q^T f of the grown
+// basis and the last pass's tail solves R gamma = c (Alg. 2, last line):
+// the first pass adds Q^T f to its block dot products, the norm pass adds
+// w^T f (c_k = w^T f / R_kk); *rhs_done reports whether that happened.
+aa_status qr_add_impl(aa_ctx* c, const double* v, const double* f = nullptr,
+                      bool* rhs_done = nullptr) {
   const int k = c->k;
   if (k >= c->cap) return AA_ESTATE;
+  const bool fuse = f != nullptr && k >= 1 && k + 1 <= 64 && c->variant != AA_MGS;
+  if (rhs_done) *rhs_done = fuse;
+  const int zf = fuse ? 1 : 0;  // one more vector read by each fused pass
   const hipStream_t st = c->stream;
   const int G = grid_stream(c);
   double* slotk = c->Q + (int64_t)k * c->ldq;
@@ -204,8 +228,13 @@ aa_status qr_add_impl(aa_ctx* c, const double* v) {
       }
       case AA_CGS2: {
         d.nx = k;
-        chk(timed(c, AA_K_DOTS, k + 1,
-                  [&] { return launch_dots(d, c->sm, tail(TAIL_CGS2_S, k), G, st); }));
+        Tail ts = tail(TAIL_CGS2_S, k);
+        if (fuse) {
+          d.z = f; d.nz = k;
+          ts.rhs = 1; ts.zoff = k;
+        }
+        chk(timed(c, AA_K_DOTS, k + 1 + zf,
+                  [&] { return launch_dots(d, c->sm, ts, G, st); }));
         Cgs2bArgs b{c->Q, c->ldq, c->n, v, k, c->sm.coef0};
         const int Gb = grid_rows(c, c->grid_stream_max);
         chk(timed(c, AA_K_CGS2B, k + 1,
@@ -213,7 +242,11 @@ aa_status qr_add_impl(aa_ctx* c, const double* v) {
         UpdArgs uc = u;
         uc.v = v; uc.out = slotk; uc.j0 = 0; uc.nc = k; uc.c1 = c->sm.coef0; uc.c2 = c->sm.coef1;
         uc.nrm = 1;
-        chk(timed(c, AA_K_UPDATE, k + 2, [&] { return launch_update(uc, c->sm, tn, G, st); }));
+        if (fuse) {
+          uc.rhsv = f;
+          tn.rhs = 1;
+        }
+        chk(timed(c, AA_K_UPDATE, k + 2 + zf, [&] { return launch_update(uc, c->sm, tn, G, st); }));
         c->syncs_add += 3;
         break;
       }
@@ -221,11 +254,20 @@ aa_status qr_add_impl(aa_ctx* c, const double* v) {
         d.nx = k;
         d.y = c->Q + (int64_t)(k - 1) * c->ldq;
         d.ny = k - 1;
-        chk(timed(c, AA_K_DOTS, k + 1,
-                  [&] { return launch_dots(d, c->sm, tail(TAIL_ICWY, k), G, st); }));
+        Tail ti = tail(TAIL_ICWY, k);
+        if (fuse) {
+          d.z = f; d.nz = k;
+          ti.rhs = 1; ti.zoff = 2 * k - 1;
+        }
+        chk(timed(c, AA_K_DOTS, k + 1 + zf,
+                  [&] { return launch_dots(d, c->sm, ti, G, st); }));
         UpdArgs ub = u;
         ub.v = v; ub.out = slotk; ub.j0 = 0; ub.nc = k; ub.c1 = c->sm.coef0; ub.nrm = 1;
-        chk(timed(c, AA_K_UPDATE, k + 2, [&] { return launch_update(ub, c->sm, tn, G, st); }));
+        if (fuse) {
+          ub.rhsv = f;
+          tn.rhs = 1;
+        }
+        chk(timed(c, AA_K_UPDATE, k + 2 + zf, [&] { return launch_update(ub, c->sm, tn, G, st); }));
         c->syncs_add += 2;
         break;
       }
@@ -238,15 +280,23 @@ aa_status qr_add_impl(aa_ctx* c, const double* v) {
         Tail ta = tail(TAIL_DCGS2, k);
         ta.reorth = reorth;
         ta.literal = (c->flags & AA_DCGS2_LITERAL) ? 1 : 0;
-        chk(timed(c, AA_K_DOTS, k + 1, [&] { return launch_dots(d, c->sm, ta, G, st); }));
+        if (fuse) {
+          d.z = f; d.nz = k;
+          ta.rhs = 1; ta.zoff = k + d.ny;
+        }
+        chk(timed(c, AA_K_DOTS, k + 1 + zf, [&] { return launch_dots(d, c->sm, ta, G, st); }));
         UpdArgs ub = u;
         ub.v = v; ub.out = slotk; ub.c1 = Rcol; ub.nrm = 1;
+        if (fuse) {
+          ub.rhsv = f;
+          tn.rhs = 1;
+        }
         if (reorth) {
           ub.dcgs2_p = k - 1; ub.reorth = 1; ub.s = c->sm.coef1; ub.j0 = 0; ub.nc = k - 1;
         } else {
           ub.j0 = 0; ub.nc = k;
         }
-        chk(timed(c, AA_K_UPDATE, k + (reorth ? 3 : 2),
+        chk(timed(c, AA_K_UPDATE, k + (reorth ? 3 : 2) + zf,
                   [&] { return launch_update(ub, c->sm, tn, G, st); }));
         c->syncs_add += 2;
         break;
@@ -476,8 +526,10 @@ aa_status aa_step(aa_ctx* c, const double* x, const double* g, double* x_next) {
     return AA_EHIP;
   aa_status s = AA_OK;
   if (i > m) s = qr_delete_impl(c);        // Alg. 2: QRDelete when the window is full
-  if (s == AA_OK) s = qr_add_impl(c, c->W);  // Alg. 2: QRAdd of Delta f_{i-1}
-  if (s == AA_OK) s = rhs_impl(c, c->f_prev);  // R gamma = Q^T f_i
+  bool rhs_done = false;
+  if (s == AA_OK)  // Alg. 2: QRAdd of Delta f_{i-1} (optionally also solving R gamma = Q^T f_i)
+    s = qr_add_impl(c, c->W, (c->flags & AA_FUSE_RHS) ? c->f_prev : nullptr, &rhs_done);
+  if (s == AA_OK && !rhs_done) s = rhs_impl(c, c->f_prev);  // R gamma = Q^T f_i
   if (s != AA_OK) return s;
   XupdArgs xa{c->ring, c->ldq, m, (int)((i - m_i) % m), m_i, g, x, x_next, c->n, c->sm.gamma};
   if (timed(c, AA_K_XUPDATE, m_i + 3,
@@ -603,8 +655,9 @@ aa_status aa_destroy(aa_ctx* c) {
 aa_status aa_profile_enable(aa_ctx* c, int enable) {
   if (!c) return AA_EINVAL;
   if (enable && c->ev.empty()) {
-    c->ev.resize(2 * kEventPairs);
+    c->ev.resize(3 * kEventPairs);
     c->ev_kind.resize(kEventPairs);
+    c->ev_mid.resize(kEventPairs);
     for (auto& e : c->ev)
       if (hipEventCreate(&e) != hipSuccess) return AA_EHIP;
   }

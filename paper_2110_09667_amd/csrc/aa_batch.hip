@@ -184,9 +184,9 @@ __device__ void wg_qr_delete(const BInst& I, int variant, int k, L& lds) {
       constexpr int KG = L::KG;
       using S = GramShape<KG>;
       v4d acc[S::NBP];
-      rotate_gram_body<KG>(r, lds.gc, lds.gs, 0, 1, lds.stage, acc);
+      rotate_gram_body<KG>(r, lds.gc, lds.gs, 0, 1, lds.stage, S::KP, acc);
       __syncthreads();
-      gram_store<KG>(acc, lds.stage + (threadIdx.x >> 6) * S::NP);
+      gram_store<KG>(acc, lds.stage + (threadIdx.x >> 6) * S::NP, k - 1);
       __syncthreads();
       const int kk = k - 1, nred = kk * (kk - 1) / 2;
       for (int c = threadIdx.x; c < nred; c += kWG) {

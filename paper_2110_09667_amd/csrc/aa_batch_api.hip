@@ -6,6 +6,7 @@
 // block.  aa_batch_run enqueues one persistent launch per iteration (after a
 // one-thread reset of the work counter); with a non-NULL stream the sequence
 // for a given iteration count is captured once as a HIP graph and replayed.
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -29,6 +30,7 @@ struct aa_batch {
   unsigned* d_counter = nullptr;
   std::vector<int64_t> n;
   std::vector<int> m;
+  std::vector<int> dim;
   int kbucket = 8;
   bool gram = false;
   int grid = 0;        // persistent workgroups (0: 2 per compute unit)
@@ -214,6 +216,7 @@ aa_status aa_batch_init(aa_batch** out, int count, const aa_batch_instance* inst
     st.pending = st.g_valid = 0;
     b->n.push_back(A.n);
     b->m.push_back(m);
+    b->dim.push_back(A.dim);
     mmax = std::max(mmax, m);
   }
   b->kbucket = bucket(mmax);
@@ -253,6 +256,99 @@ aa_status aa_batch_set_schedule(aa_batch* b, int grid, int order, int use_graph)
   b->order_mode = order;
   b->use_graph = use_graph != 0;
   drop_graph(b);
+  return AA_OK;
+}
+
+aa_status aa_batch_autotune(aa_batch* b, int iters, const char* cache_path,
+                            aa_batch_schedule* best) {
+  if (!b || iters < 1) return AA_EINVAL;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return AA_EHIP;
+  const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  // FNV-1a over the workload: variant, flags, every instance's (n, m, dim)
+  uint64_t sig = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      sig ^= (v >> (8 * i)) & 0xffu;
+      sig *= 1099511628211ull;
+    }
+  };
+  mix((uint64_t)b->variant);
+  mix((uint64_t)b->flags);
+  for (int j = 0; j < b->count; ++j) {
+    mix((uint64_t)b->n[j]);
+    mix((uint64_t)b->m[j]);
+    mix((uint64_t)b->dim[j]);
+  }
+  char sigs[32];
+  snprintf(sigs, sizeof sigs, "%016llx", (unsigned long long)sig);
+  const bool graph = b->use_graph;
+  if (cache_path) {
+    // the last line matching this device and workload wins
+    bool hit = false;
+    aa_batch_schedule got{0, 0, 0.0, 0};
+    if (FILE* fh = fopen(cache_path, "r")) {
+      char arch[128], s2[64];
+      int g = 0, o = 0;
+      double ms = 0.0;
+      while (fscanf(fh, "%127s %63s %d %d %lf", arch, s2, &g, &o, &ms) == 5)
+        if (strcmp(arch, prop.gcnArchName) == 0 && strcmp(s2, sigs) == 0 && g >= 0 && o >= 0 &&
+            o <= 1) {
+          hit = true;
+          got = aa_batch_schedule{g, o, ms, 0};
+        }
+      fclose(fh);
+    }
+    if (hit) {
+      const aa_status st = aa_batch_set_schedule(b, got.grid, got.order, graph);
+      if (st != AA_OK) return st;
+      if (best) *best = got;
+      return AA_OK;
+    }
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return AA_EHIP;
+  }
+  aa_status st = AA_OK;
+  aa_batch_schedule win{0, 0, 1e300, 0};
+  for (int per = 1; per <= 4 && st == AA_OK; ++per) {
+    const int g = std::min(per * cus, b->count);
+    if (per > 1 && g == std::min((per - 1) * cus, b->count)) break;  // capped: no new candidate
+    for (int o = 0; o <= 1 && st == AA_OK; ++o) {
+      st = aa_batch_set_schedule(b, g, o, 0);
+      if (st != AA_OK) break;
+      float ms = 0.f;
+      if (hipEventRecord(e0, b->stream) != hipSuccess || enqueue(b, iters) != hipSuccess ||
+          hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = AA_EHIP;
+        break;
+      }
+      win.trials += 1;
+      if (ms / iters < win.ms_per_iter) {
+        win.grid = g;
+        win.order = o;
+        win.ms_per_iter = ms / iters;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != AA_OK) return st;
+  st = aa_batch_set_schedule(b, win.grid, win.order, graph);
+  if (st != AA_OK) return st;
+  if (cache_path) {
+    if (FILE* fh = fopen(cache_path, "a")) {
+      fprintf(fh, "%s %s %d %d %.6f\n", prop.gcnArchName, sigs, win.grid, win.order,
+              win.ms_per_iter);
+      fclose(fh);
+    }
+  }
+  if (best) *best = win;
   return AA_OK;
 }
 

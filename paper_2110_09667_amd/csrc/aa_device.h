@@ -49,8 +49,48 @@ __device__ __forceinline__ double multi_reduce(double (&v)[N]) {
 
 // ---------------------------------------------------------------------------
 // row loads for the streaming passes: each lane owns kPairs pairs of
-// consecutive rows (16-byte loads), pair i at rows b2 + 2 i kWG + {0, 1}
+// consecutive rows (16-byte loads), pair i at rows b2 + 2 i kWG + {0, 1}.
+// Full tiles use non-temporal loads (AA_NT_LOAD): the streamed columns are
+// far larger than the caches and are not re-read within a pass, and marking
+// them streaming measurably raises the sustained read bandwidth.
 // ---------------------------------------------------------------------------
+
+#ifndef AA_NT_LOAD
+#define AA_NT_LOAD 1
+#endif
+#ifndef AA_NT_STORE
+#define AA_NT_STORE 0
+#endif
+
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// One streamed 16-byte pair.
+__device__ __forceinline__ f64x2 ld2v(const double2* p) {
+#if AA_NT_LOAD
+  return __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p));
+#else
+  const double2 v = *p;
+  f64x2 r;
+  r.x = v.x;
+  r.y = v.y;
+  return r;
+#endif
+}
+
+// Store one 16-byte pair that no later pass of this call reads back soon
+// (non-temporal: the written columns far exceed the caches).
+__device__ __forceinline__ void st2v_stream(f64x2 v, double* p) {
+  __builtin_nontemporal_store(v, reinterpret_cast<f64x2*>(p));
+}
+
+// One streamed value (the row-per-thread sweeps).
+__device__ __forceinline__ double ld1(const double* p) {
+#if AA_NT_LOAD
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
 
 template <bool FULL>
 __device__ __forceinline__ void ld2(double2 (&r)[kPairs], const double* __restrict__ p,
@@ -59,7 +99,12 @@ __device__ __forceinline__ void ld2(double2 (&r)[kPairs], const double* __restri
   for (int i = 0; i < kPairs; ++i) {
     const int64_t row = b2 + (int64_t)i * 2 * kWG;
     if (FULL) {
+#if AA_NT_LOAD
+      const f64x2 v = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p + row));
+      r[i] = make_double2(v.x, v.y);
+#else
       r[i] = *reinterpret_cast<const double2*>(p + row);
+#endif
     } else {
       r[i].x = row < n ? p[row] : 0.0;
       r[i].y = row + 1 < n ? p[row + 1] : 0.0;
@@ -74,7 +119,14 @@ __device__ __forceinline__ void st2(const double2 (&r)[kPairs], double* p, int64
   for (int i = 0; i < kPairs; ++i) {
     const int64_t row = b2 + (int64_t)i * 2 * kWG;
     if (FULL) {
+#if AA_NT_STORE
+      f64x2 v;
+      v.x = r[i].x;
+      v.y = r[i].y;
+      __builtin_nontemporal_store(v, reinterpret_cast<f64x2*>(p + row));
+#else
       *reinterpret_cast<double2*>(p + row) = r[i];
+#endif
     } else {
       if (row < n) p[row] = r[i].x;
       if (row + 1 < n) p[row + 1] = r[i].y;

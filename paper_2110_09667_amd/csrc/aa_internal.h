@@ -17,7 +17,7 @@ constexpr int kWaves = kWG / 64;
 constexpr int kPairs = AA_PAIRS;     // row pairs (16-byte loads) per lane per tile
 constexpr int kTile = kWG * 2 * kPairs;  // rows per tile in streaming passes
 constexpr int kMaxCols = AA_MAX_COLS;
-constexpr int kMaxRed = 2 * kMaxCols + 4;  // reductions of one streaming pass
+constexpr int kMaxRed = 3 * kMaxCols + 4;  // reductions of one streaming pass
 constexpr int kMaxPairs = (kMaxCols - 1) * (kMaxCols - 2) / 2;  // Gram after delete
 constexpr int kMaxRedAll = kMaxPairs > kMaxRed ? kMaxPairs : kMaxRed;
 constexpr int kFinWG = 1024;         // threads of the finalize kernel
@@ -64,16 +64,20 @@ struct Tail {
   int idx;      // TAIL_NORM: index of the squared norm in red[]
   int reorth;   // TAIL_DCGS2
   int literal;  // TAIL_DCGS2
+  int rhs;      // R gamma = Q^T f folded into the QRAdd passes (see aa_step)
+  int zoff;     // first QRAdd pass with rhs: index of Q^T f in red[]
 };
 
 // ---- streaming passes -------------------------------------------------------
 
-// red[j] = Q_j^T x (j < nx); red[nx + j] = Q_j^T y (j < ny); red[nx+ny] = x^T x
+// red[j] = Q_j^T x (j < nx); red[nx + j] = Q_j^T y (j < ny);
+// red[nx + ny + j] = Q_j^T z (j < nz); red[nx + ny + nz] = x^T x
 struct DotsArgs {
   const double* Q; int64_t ldq; int64_t n;
   const double* x; int nx;
   const double* y; int ny;
   int xx;
+  const double* z; int nz;
 };
 
 // out = v - sum_{j0 <= j < j0+nc} Q_j (c1[j] + c2[j]) evaluated as
@@ -94,6 +98,7 @@ struct UpdArgs {
   int dcgs2_p;           // -1: off
   int reorth;
   const double* s;       // DCGS-2 reorthogonalization coefficients
+  const double* rhsv;    // may be null: add out^T rhsv after the norm
 };
 
 struct Cgs2bArgs {       // y = v - Q s (registers), red[j] = Q_j^T y
@@ -187,6 +192,11 @@ hipError_t launch_batch_reset(unsigned* counter, hipStream_t);
 hipError_t launch_batch_init(BInst* inst, int count, hipStream_t);
 
 // launchers (aa_kernels.hip)
+// Profiling hook: while set, the next finalize launch records this event on
+// its stream first (separating a pass from its finalize kernel).
+void set_profile_mid(hipEvent_t e);
+bool profile_mid_used();
+
 hipError_t launch_dots(const DotsArgs&, const Small&, const Tail&, int grid, hipStream_t);
 hipError_t launch_update(const UpdArgs&, const Small&, const Tail&, int grid, hipStream_t);
 hipError_t launch_cgs2b(const Cgs2bArgs&, const Small&, const Tail&, int grid, hipStream_t);

@@ -31,18 +31,35 @@ __device__ void publish(const Small& sm, int nred, const double* acc, int acc_st
   }
 }
 
+// Sum of the G partials of one value by one wave: lane l adds partials
+// l, l + 64, ... into eight interleaved accumulators (eight independent loads
+// in flight per lane), combined in a fixed tree, then across the lanes.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ p, int G, int lane) {
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int g = lane;
+  for (; g + 7 * 64 < G; g += 8 * 64) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += p[g + u * 64];
+  }
+  for (int u = 0; g < G; g += 64, ++u) a[u & 7] += p[g];
+  const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  return wave_sum(s);
+}
+
 // Fixed-order sum of the G partials of each of the nred values (one wave per
-// value, lanes strided over the workgroups), then the dense tail.
+// value, two values per wave in flight), then the dense tail.
 __global__ __launch_bounds__(kFinWG) void k_finalize(Small sm, Tail t, int nred, int G) {
   __shared__ double red[kMaxRedAll];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   constexpr int waves = kFinWG / 64;
-  for (int c = w; c < nred; c += waves) {
-    const double* p = sm.partials + (size_t)c * G;
-    double s = 0.0;
-    for (int g = lane; g < G; g += 64) s += p[g];
-    s = wave_sum(s);
-    if (lane == 0) red[c] = s;
+  for (int c = w; c < nred; c += 2 * waves) {
+    const int c2 = c + waves;
+    const double s1 = sum_partials(sm.partials + (size_t)c * G, G, lane);
+    const double s2 = c2 < nred ? sum_partials(sm.partials + (size_t)c2 * G, G, lane) : 0.0;
+    if (lane == 0) {
+      red[c] = s1;
+      if (c2 < nred) red[c2] = s2;
+    }
   }
   __syncthreads();
   run_tail(sm, t, red);
@@ -91,18 +108,17 @@ __global__ __launch_bounds__(kWG) void k_rotate(RotArgs a, Small sm) {
 
 template <int KMAX>
 __global__ __launch_bounds__(kWG) void k_rotate_gram(RotArgs a, Small sm) {
-  using S = GramShape<KMAX>;
-  constexpr int ACC = kWaves * S::NP;
-  __shared__ double s_buf[S::STAGE > ACC ? S::STAGE : ACC];
+  // staging rows, then the per-wave pair sums: gram_lds_doubles(k - 1) doubles
+  extern __shared__ double s_buf[];
   __shared__ double s_c[KMAX], s_s[KMAX];
+  const int kk = a.k - 1, np = kk * (kk - 1) / 2;
   givens_coefs(a, sm.cap, s_c, s_s, KMAX);
   __syncthreads();
-  v4d acc[S::NBP];
-  rotate_gram_body<KMAX>(a, s_c, s_s, blockIdx.x, gridDim.x, s_buf, acc);
+  v4d acc[GramShape<KMAX>::NBP];
+  rotate_gram_body<KMAX>(a, s_c, s_s, blockIdx.x, gridDim.x, s_buf, gram_stride(kk), acc);
   __syncthreads();  // the staging area becomes the per-wave pair accumulators
-  gram_store<KMAX>(acc, s_buf + (threadIdx.x >> 6) * S::NP);
-  const int kk = a.k - 1;
-  publish(sm, kk * (kk - 1) / 2, s_buf, S::NP);
+  gram_store<KMAX>(acc, s_buf + (threadIdx.x >> 6) * np, kk);
+  publish(sm, np, s_buf, np);
 }
 
 __global__ __launch_bounds__(kWG) void k_scale(ScaleArgs a) {
@@ -157,10 +173,27 @@ __global__ void k_copy(double* dst, const double* src, int64_t n) {
 // launchers
 // ---------------------------------------------------------------------------
 
+namespace {
+thread_local hipEvent_t t_prof_mid = nullptr;
+thread_local bool t_prof_mid_used = false;
+}  // namespace
+
+void set_profile_mid(hipEvent_t e) {
+  t_prof_mid = e;
+  t_prof_mid_used = false;
+}
+
+bool profile_mid_used() { return t_prof_mid_used; }
+
 static hipError_t launch_finalize(const Small& sm, const Tail& t, int nred, int grid,
                                   hipStream_t st) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (t_prof_mid) {
+    e = hipEventRecord(t_prof_mid, st);
+    if (e != hipSuccess) return e;
+    t_prof_mid_used = true;
+  }
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinWG), 0, st, sm, t, nred, grid);
   return hipGetLastError();
 }
@@ -169,14 +202,14 @@ hipError_t launch_dots(const DotsArgs& a, const Small& sm, const Tail& t, int gr
                        hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
   hipLaunchKernelGGL(k_dots, dim3(grid), dim3(kWG), 0, st, a, sm);
-  return launch_finalize(sm, t, a.nx + a.ny + (a.xx ? 1 : 0), grid, st);
+  return launch_finalize(sm, t, a.nx + a.ny + a.nz + (a.xx ? 1 : 0), grid, st);
 }
 
 hipError_t launch_update(const UpdArgs& a, const Small& sm, const Tail& t, int grid,
                          hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
   hipLaunchKernelGGL(k_update, dim3(grid), dim3(kWG), 0, st, a, sm);
-  return launch_finalize(sm, t, (a.dotcol >= 0 ? 1 : 0) + (a.nrm ? 1 : 0), grid, st);
+  return launch_finalize(sm, t, update_nred(a), grid, st);
 }
 
 hipError_t launch_cgs2b(const Cgs2bArgs& a, const Small& sm, const Tail& t, int grid,
@@ -203,12 +236,15 @@ hipError_t launch_rotate(const RotArgs& a, const Small& sm, const Tail& t, int g
                          hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
   if (a.gram) {
+    // dynamic LDS sized for the live columns: fewer columns, more resident
+    // workgroups per compute unit
+    const size_t lds = sizeof(double) * (size_t)gram_lds_doubles(a.k - 1);
     if (a.k <= 16)
-      hipLaunchKernelGGL(k_rotate_gram<16>, dim3(grid), dim3(kWG), 0, st, a, sm);
+      hipLaunchKernelGGL(k_rotate_gram<16>, dim3(grid), dim3(kWG), lds, st, a, sm);
     else if (a.k <= 32)
-      hipLaunchKernelGGL(k_rotate_gram<32>, dim3(grid), dim3(kWG), 0, st, a, sm);
+      hipLaunchKernelGGL(k_rotate_gram<32>, dim3(grid), dim3(kWG), lds, st, a, sm);
     else if (a.k <= 64)
-      hipLaunchKernelGGL(k_rotate_gram<64>, dim3(grid), dim3(kWG), 0, st, a, sm);
+      hipLaunchKernelGGL(k_rotate_gram<64>, dim3(grid), dim3(kWG), lds, st, a, sm);
     else
       return hipErrorInvalidValue;  // the ICWY window is limited to 64 columns
     return launch_finalize(sm, t, (a.k - 1) * (a.k - 2) / 2, grid, st);

@@ -17,6 +17,23 @@ namespace aa {
 // dense tails, run by one workgroup once the reduced values are in red[]
 // ---------------------------------------------------------------------------
 
+// Back substitution R gamma = c (Alg. 2, last line) by one wave: lane l < k1
+// holds c_l in x on entry.  c is also kept in coef1 (free after QRAdd; the
+// learned step reads it as a feature).  Threads past the first wave return.
+__device__ __forceinline__ void rhs_backsolve(const Small& sm, int k1, double x) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid >= 64) return;
+  const int cap = sm.cap;
+  if (lane < k1) sm.coef1[lane] = x;
+  double gam = 0.0;
+  for (int a = k1 - 1; a >= 0; --a) {
+    const double ga = __shfl(x, a, 64) / sm.R[a + (size_t)a * cap];
+    if (lane < a) x -= sm.R[lane + (size_t)a * cap] * ga;
+    if (lane == a) gam = ga;
+  }
+  if (lane < k1) sm.gamma[lane] = gam;
+}
+
 __device__ inline void run_tail(const Small& sm, const Tail& t, const double* red) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int nthr = blockDim.x;
@@ -31,15 +48,26 @@ __device__ inline void run_tail(const Small& sm, const Tail& t, const double* re
     case TAIL_MGS_R:
       if (tid == 0) R[t.row + (size_t)k * cap] = red[0];
       break;
-    case TAIL_NORM:
+    case TAIL_NORM: {
+      const double nv = sqrt(red[t.idx]);
       if (tid == 0) {
-        const double nv = sqrt(red[t.idx]);
         R[k + (size_t)k * cap] = nv;
         if (!(nv > 0.0) || !isfinite(nv)) *sm.status = AA_EBREAKDOWN;
       }
+      if (t.rhs) {
+        // c_k = q_k^T f = (w^T f) / R_kk; c_0..c_{k-1} were stashed in gamma
+        // by the first pass of this QRAdd.  Then R gamma = c.
+        __syncthreads();
+        const double x = lane < k ? sm.gamma[lane] : (lane == k ? red[t.idx + 1] / nv : 0.0);
+        __syncthreads();
+        rhs_backsolve(sm, k + 1, x);
+      }
       break;
+    }
     case TAIL_CGS2_S:
       for (int i = tid; i < k; i += nthr) sm.coef0[i] = red[i];
+      if (t.rhs)
+        for (int i = tid; i < k; i += nthr) sm.gamma[i] = red[t.zoff + i];
       break;
     case TAIL_CGS2_Z:
       for (int i = tid; i < k; i += nthr) {
@@ -53,6 +81,8 @@ __device__ inline void run_tail(const Small& sm, const Tail& t, const double* re
       // substitution, one lane per row); r' is column k of R and the
       // coefficients of the update pass.
       for (int b = tid; b < k - 1; b += nthr) T[(k - 1) + (size_t)b * cap] = red[k + b];
+      if (t.rhs)
+        for (int i = tid; i < k; i += nthr) sm.gamma[i] = red[t.zoff + i];
       if (tid < 64) {
         double x = (lane < k) ? red[lane] : 0.0;
         for (int b = 0; b < k; ++b) {
@@ -82,21 +112,21 @@ __device__ inline void run_tail(const Small& sm, const Tail& t, const double* re
           R[i + (size_t)p * cap] += scale * s;
         }
       }
+      if (t.rhs) {
+        // Q^T f with the columns as they stand after this add: only q_{k-1}
+        // changes (q_{k-1} - Q_{:,0:k-2} s, not renormalized)
+        for (int i = tid; i < k - 1; i += nthr) sm.gamma[i] = red[t.zoff + i];
+        if (tid == 0) {
+          double ck = red[t.zoff + k - 1];
+          if (t.reorth)
+            for (int i = 0; i < k - 1; ++i) ck -= red[k + i] * red[t.zoff + i];
+          sm.gamma[k - 1] = ck;
+        }
+      }
       break;
     case TAIL_RHS:
-      // Alg. 2, last line: back substitution R gamma = c, c = Q^T f_i (c is
-      // kept in coef1, free after QRAdd, for the learned step's features).
-      if (tid < 64) {
-        double x = (lane < k) ? red[lane] : 0.0;
-        if (lane < k) sm.coef1[lane] = x;
-        double gam = 0.0;
-        for (int a = k - 1; a >= 0; --a) {
-          const double ga = __shfl(x, a, 64) / R[a + (size_t)a * cap];
-          if (lane < a) x -= R[lane + (size_t)a * cap] * ga;
-          if (lane == a) gam = ga;
-        }
-        if (lane < k) sm.gamma[lane] = gam;
-      }
+      // Alg. 2, last line: back substitution R gamma = c, c = Q^T f_i
+      rhs_backsolve(sm, k, lane < k ? red[lane] : 0.0);
       break;
     case TAIL_RES:
       if (tid == 0) sm.scal[S_RES] = red[0];
@@ -149,19 +179,23 @@ __device__ __forceinline__ void lds_zero(double* p, int n) {
 // (j < ny); acc_w[nx + ny] += x^T x
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int dots_nred(const DotsArgs& a) { return a.nx + a.ny + (a.xx ? 1 : 0); }
+__device__ __forceinline__ int dots_nred(const DotsArgs& a) {
+  return a.nx + a.ny + a.nz + (a.xx ? 1 : 0);
+}
 
 __device__ inline void dots_body(const DotsArgs& a, int64_t t0, int64_t ts, double* acc) {
   const int lane = threadIdx.x & 63;
-  const int nq = a.nx > a.ny ? a.nx : a.ny;
+  int nq = a.nx > a.ny ? a.nx : a.ny;
+  if (a.nz > nq) nq = a.nz;
   for_tiles(a.n, t0, ts, [&](int64_t b2, auto full) {
     constexpr bool F = decltype(full)::value;
-    double2 xv[kPairs], yv[kPairs];
+    double2 xv[kPairs], yv[kPairs], zv[kPairs];
     ld2<F>(xv, a.x, b2, a.n);
     if (a.ny > 0) ld2<F>(yv, a.y, b2, a.n);
+    if (a.nz > 0) ld2<F>(zv, a.z, b2, a.n);
     if (a.xx) {
       const double p = wave_sum(dot2(xv, xv));
-      if (lane == 0) acc[a.nx + a.ny] += p;
+      if (lane == 0) acc[a.nx + a.ny + a.nz] += p;
     }
     for (int j0 = 0; j0 < nq; j0 += kGroup) {
       double2 q[kGroup][kPairs];
@@ -172,7 +206,27 @@ __device__ inline void dots_body(const DotsArgs& a, int64_t t0, int64_t ts, doub
         else
           zero2(q[c]);
       }
-      if (a.ny > 0) {
+      if (a.nz > 0) {
+        // three right-hand sides: x, y, z (and a zero block to make 4 kGroup)
+        double v[4 * kGroup];
+#pragma unroll
+        for (int c = 0; c < kGroup; ++c) {
+          v[c] = (j0 + c < a.nx) ? dot2(q[c], xv) : 0.0;
+          v[kGroup + c] = (j0 + c < a.ny) ? dot2(q[c], yv) : 0.0;
+          v[2 * kGroup + c] = (j0 + c < a.nz) ? dot2(q[c], zv) : 0.0;
+          v[3 * kGroup + c] = 0.0;
+        }
+        const double r = multi_reduce<4 * kGroup>(v);
+        if (lane < kGroup) {
+          if (j0 + lane < a.nx) acc[j0 + lane] += r;
+        } else if (lane < 2 * kGroup) {
+          const int j = j0 + lane - kGroup;
+          if (j < a.ny) acc[a.nx + j] += r;
+        } else if (lane < 3 * kGroup) {
+          const int j = j0 + lane - 2 * kGroup;
+          if (j < a.nz) acc[a.nx + a.ny + j] += r;
+        }
+      } else if (a.ny > 0) {
         double v[2 * kGroup];
 #pragma unroll
         for (int c = 0; c < kGroup; ++c) {
@@ -202,8 +256,8 @@ __device__ inline void dots_body(const DotsArgs& a, int64_t t0, int64_t ts, doub
 // acc_w[0] += Q_dotcol^T out (if dotcol >= 0); acc_w[inorm] += out^T out
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int update_nred(const UpdArgs& a) {
-  return (a.dotcol >= 0 ? 1 : 0) + (a.nrm ? 1 : 0);
+__host__ __device__ __forceinline__ int update_nred(const UpdArgs& a) {
+  return (a.dotcol >= 0 ? 1 : 0) + (a.nrm ? 1 : 0) + (a.rhsv ? 1 : 0);
 }
 
 // Coefficients of an update pass copied to LDS (read once per workgroup).
@@ -288,6 +342,12 @@ __device__ inline void update_body(const UpdArgs& a, const double* s_c1, const d
     if (a.nrm) {
       const double p = wave_sum(dot2(o, o));
       if (lane == 0) acc[inorm] += p;
+    }
+    if (a.rhsv) {
+      double2 fv[kPairs];
+      ld2<F>(fv, a.rhsv, b2, a.n);
+      const double p = wave_sum(dot2(fv, o));
+      if (lane == 0) acc[inorm + (a.nrm ? 1 : 0)] += p;
     }
   });
 }
@@ -407,11 +467,11 @@ __device__ __forceinline__ void rotate_row(const RotArgs& a, int64_t row, bool v
   const int kk = a.k - 1;
   const double* qrow = a.Q + row;
   double* qw = a.Q + row;
-  double x = valid ? qrow[0] : 0.0;
+  double x = valid ? ld1(qrow) : 0.0;
   double nxt[kRotCh];
 #pragma unroll
   for (int c = 0; c < kRotCh; ++c)
-    nxt[c] = (valid && 1 + c < a.k) ? qrow[(int64_t)(1 + c) * a.ldq] : 0.0;
+    nxt[c] = (valid && 1 + c < a.k) ? ld1(qrow + (int64_t)(1 + c) * a.ldq) : 0.0;
   for (int j0 = 0; j0 < kk; j0 += kRotCh) {
     double cur[kRotCh];
 #pragma unroll
@@ -419,7 +479,7 @@ __device__ __forceinline__ void rotate_row(const RotArgs& a, int64_t row, bool v
 #pragma unroll
     for (int c = 0; c < kRotCh; ++c) {
       const int jn = j0 + kRotCh + 1 + c;
-      nxt[c] = (valid && jn < a.k) ? qrow[(int64_t)jn * a.ldq] : 0.0;
+      nxt[c] = (valid && jn < a.k) ? ld1(qrow + (int64_t)jn * a.ldq) : 0.0;
     }
 #pragma unroll
     for (int c = 0; c < kRotCh; ++c) {
@@ -436,12 +496,56 @@ __device__ __forceinline__ void rotate_row(const RotArgs& a, int64_t row, bool v
   }
 }
 
+// The same sweep for two adjacent rows (row even, row + 1 < n) with 16-byte
+// loads and stores.
+__device__ __forceinline__ void rotate_pair(const RotArgs& a, int64_t row, const double* s_c,
+                                            const double* s_s) {
+  const int kk = a.k - 1;
+  const double* qrow = a.Q + row;
+  f64x2 x = ld2v(reinterpret_cast<const double2*>(qrow));
+  f64x2 nxt[kRotCh];
+#pragma unroll
+  for (int c = 0; c < kRotCh; ++c)
+    nxt[c] = (1 + c < a.k) ? ld2v(reinterpret_cast<const double2*>(qrow + (int64_t)(1 + c) * a.ldq))
+                           : f64x2{0.0, 0.0};
+  for (int j0 = 0; j0 < kk; j0 += kRotCh) {
+    f64x2 cur[kRotCh];
+#pragma unroll
+    for (int c = 0; c < kRotCh; ++c) cur[c] = nxt[c];
+#pragma unroll
+    for (int c = 0; c < kRotCh; ++c) {
+      const int jn = j0 + kRotCh + 1 + c;
+      nxt[c] = jn < a.k ? ld2v(reinterpret_cast<const double2*>(qrow + (int64_t)jn * a.ldq))
+                        : f64x2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int c = 0; c < kRotCh; ++c) {
+      const int j = j0 + c;
+      if (j < kk) {
+        const f64x2 y = cur[c];
+        const double cj = s_c[j], sj = s_s[j];
+        f64x2 qn;
+        qn.x = cj * x.x + sj * y.x;
+        qn.y = cj * x.y + sj * y.y;
+        x.x = -sj * x.x + cj * y.x;
+        x.y = -sj * x.y + cj * y.y;
+        st2v_stream(qn, a.Q + row + (int64_t)j * a.ldq);
+      }
+    }
+  }
+}
+
+// Row pairs p = tile kWG + tid (rows 2p, 2p + 1); an odd last row alone.
 __device__ inline void rotate_body(const RotArgs& a, const double* s_c, const double* s_s,
                                    int64_t t0, int64_t ts) {
-  const int64_t ntiles = (a.n + kWG - 1) / kWG;
+  const int64_t npair = (a.n + 1) / 2;
+  const int64_t ntiles = (npair + kWG - 1) / kWG;
   for (int64_t tile = t0; tile < ntiles; tile += ts) {
-    const int64_t row = tile * kWG + threadIdx.x;
-    rotate_row(a, row, row < a.n, s_c, s_s, [](int, double) {});
+    const int64_t row = 2 * (tile * kWG + threadIdx.x);
+    if (row + 1 < a.n)
+      rotate_pair(a, row, s_c, s_s);
+    else if (row < a.n)
+      rotate_row(a, row, true, s_c, s_s, [](int, double) {});
   }
 }
 
@@ -450,38 +554,53 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 template <int KMAX>
 struct GramShape {
   static_assert(KMAX % 16 == 0, "Gram blocks are 16 columns wide");
-  static constexpr int KP = KMAX + 1;            // LDS row stride (doubles)
+  static constexpr int KP = KMAX + 1;            // largest LDS row stride (doubles)
   static constexpr int NB = KMAX / 16;           // 16-column blocks
   static constexpr int NBP = NB * (NB + 1) / 2;  // lower block pairs
   static constexpr int NP = KMAX * (KMAX - 1) / 2;
-  static constexpr int STAGE = kWaves * 64 * KP; // staging doubles per workgroup
+  static constexpr int STAGE = kWaves * 64 * KP; // staging doubles per workgroup (largest)
 };
 
+// LDS row stride for kk staged columns: the smallest odd number >= kk, so
+// that the 64 lanes of a wave writing one row each spread over all banks.
+__host__ __device__ constexpr int gram_stride(int kk) { return kk | 1; }
+
+// Staging doubles a workgroup needs for kk rotated columns (the same area
+// later holds the per-wave pair sums).
+__host__ __device__ constexpr int gram_lds_doubles(int kk) {
+  return kWaves * 64 * gram_stride(kk) > kWaves * (kk * (kk - 1) / 2)
+             ? kWaves * 64 * gram_stride(kk)
+             : kWaves * (kk * (kk - 1) / 2);
+}
+
 // ICWY after QRDelete (Sec. 3.2): rotate, then accumulate the strict lower
-// Gram matrix of the k-1 rotated columns, T_ab = q_a^T q_b (b < a).  The Gram
-// over rows is a dense contraction, done on the matrix cores: each wave stages
-// its 64 rotated rows in LDS (row stride KMAX + 1 doubles) and, 4 rows at a
-// time, issues v_mfma_f64_16x16x4 on every lower pair of 16-column blocks.
-// Operand layout of that instruction: lane l supplies A[l % 16][l / 16] and
-// B[l / 16][l % 16]; lane l, register r of the result holds D[l / 16 + 4 r]
-// [l % 16].  Accumulators stay in registers across all tiles of the call.
+// Gram matrix of the kk = k-1 rotated columns, T_ab = q_a^T q_b (b < a).  The
+// Gram over rows is a dense contraction, done on the matrix cores: each wave
+// stages its 64 rotated rows in LDS (row stride kp = gram_stride(kk) doubles,
+// only the kk live columns) and, 4 rows at a time, issues v_mfma_f64_16x16x4
+// on every lower pair of 16-column blocks, reading zeros for the columns past
+// kk.  Operand layout of that instruction: lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]; lane l, register r of the result holds
+// D[l / 16 + 4 r][l % 16].  Accumulators stay in registers across all tiles.
 template <int KMAX>
 __device__ inline void rotate_gram_body(const RotArgs& a, const double* s_c, const double* s_s,
-                                        int64_t t0, int64_t ts, double* stage_all,
+                                        int64_t t0, int64_t ts, double* stage_all, int kp,
                                         v4d (&acc)[GramShape<KMAX>::NBP]) {
   using S = GramShape<KMAX>;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  double* stage = stage_all + w * 64 * S::KP;
+  double* stage = stage_all + w * 64 * kp;
 #pragma unroll
   for (int p = 0; p < S::NBP; ++p) acc[p] = v4d{0.0, 0.0, 0.0, 0.0};
   const int64_t ntiles = (a.n + kWG - 1) / kWG;
   const int kk = a.k - 1;
+  bool live[S::NB];
+#pragma unroll
+  for (int b = 0; b < S::NB; ++b) live[b] = b * 16 + li < kk;
   for (int64_t tile = t0; tile < ntiles; tile += ts) {
     const int64_t row = tile * kWG + threadIdx.x;
-    double* srow = stage + lane * S::KP;
+    double* srow = stage + lane * kp;
     rotate_row(a, row, row < a.n, s_c, s_s, [&](int j, double v) { srow[j] = v; });
-    for (int j = kk; j < KMAX; ++j) srow[j] = 0.0;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -489,7 +608,7 @@ __device__ inline void rotate_gram_body(const RotArgs& a, const double* s_c, con
     for (int r0 = 0; r0 < 64; r0 += 4) {
       double v[S::NB];
 #pragma unroll
-      for (int b = 0; b < S::NB; ++b) v[b] = stage[(r0 + lk) * S::KP + b * 16 + li];
+      for (int b = 0; b < S::NB; ++b) v[b] = live[b] ? stage[(r0 + lk) * kp + b * 16 + li] : 0.0;
       int p = 0;
 #pragma unroll
       for (int bi = 0; bi < S::NB; ++bi)
@@ -503,9 +622,10 @@ __device__ inline void rotate_gram_body(const RotArgs& a, const double* s_c, con
   }
 }
 
-// Write this wave's Gram accumulators as pair sums accw[a(a-1)/2 + b], b < a.
+// Write this wave's Gram accumulators as pair sums accw[a(a-1)/2 + b],
+// b < a < kk.
 template <int KMAX>
-__device__ inline void gram_store(const v4d (&acc)[GramShape<KMAX>::NBP], double* accw) {
+__device__ inline void gram_store(const v4d (&acc)[GramShape<KMAX>::NBP], double* accw, int kk) {
   using S = GramShape<KMAX>;
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
@@ -517,7 +637,7 @@ __device__ inline void gram_store(const v4d (&acc)[GramShape<KMAX>::NBP], double
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int ia = bi * 16 + lk + 4 * r, ib = bj * 16 + li;
-        if (ia > ib) accw[ia * (ia - 1) / 2 + ib] = acc[p][r];
+        if (ia > ib && ia < kk) accw[ia * (ia - 1) / 2 + ib] = acc[p][r];
       }
 }
 
@@ -579,7 +699,7 @@ __device__ inline void scale_body(const double* in, double* out, int64_t n, doub
   const double2* in2 = reinterpret_cast<const double2*>(in);
   double2* out2 = reinterpret_cast<double2*>(out);
   for (int64_t r = t0 * kWG + threadIdx.x; r < npair; r += ts * kWG) {
-    const double2 v = in2[r];
+    const f64x2 v = ld2v(in2 + r);
     out2[r] = make_double2(v.x / d, v.y / d);
   }
   if (t0 == 0 && threadIdx.x == 0 && (n & 1)) out[n - 1] = in[n - 1] / d;

@@ -138,3 +138,37 @@ def test_batch_mixed_sizes_with_a_large_instance():
     for j, (inst, p) in enumerate(zip(insts, probs)):
         xs, _, _ = O.run_aa(lambda u: O.G_stencil(p, u), np.zeros(p.n), inst.m, "icwy", iters)
         assert rel(b.x[j].cpu().numpy(), xs[-1]) <= 1e-10, j
+
+
+def test_autotune_keeps_results_and_caches(tmp_path):
+    """The autotuner runs real iterations under each candidate schedule: the
+    iterates equal those of an untuned batch after the same number of
+    iterations; a second tuning with the same cache file runs no trial and
+    applies the stored schedule."""
+    import torch
+    device()
+    from paper_2110_09667_amd import aa
+    insts, probs = small_table(count=12, seed0=300)
+    ms = [i.m for i in insts]
+    stream = torch.cuda.Stream()
+    cache = str(tmp_path / "tune.txt")
+    with torch.cuda.stream(stream):
+        bt = aa.AABatch(probs, ms, "icwy", tol=0.0, max_iter=10**9, stream=stream)
+        bp = aa.AABatch(probs, ms, "icwy", tol=0.0, max_iter=10**9, stream=stream)
+        bt.run(13)
+        bp.run(13)
+        best = bt.autotune(2, cache)
+        assert best.trials >= 2 and best.grid >= 1 and best.ms_per_iter > 0
+        done = 13 + 2 * best.trials
+        bp.run(done - 13)
+        st, _ = bt.read()
+        sp, _ = bp.read()
+        for j in range(len(insts)):
+            assert st[j].iter == sp[j].iter == done
+            assert np.array_equal(bt.x[j].cpu().numpy(), bp.x[j].cpu().numpy())
+        again = bp.autotune(2, cache)
+        assert again.trials == 0 and again.grid == best.grid and again.order == best.order
+        assert bp.read()[0][0].iter == done
+    with open(cache) as fh:
+        lines = fh.read().split()
+    assert len(lines) == 5 and lines[0].startswith("gfx")

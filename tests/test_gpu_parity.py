@@ -281,6 +281,58 @@ def test_aa_nonlinear3d_small_matches_oracle(variant, m, fused):
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("m", [2, 3, 10, 17])
+def test_aa_fused_rhs_matches_oracle(variant, m):
+    """AA_FUSE_RHS (c = Q^T f_i formed inside the QRAdd passes, R gamma = c
+    solved in the last pass's tail) on the grid-wide path: 3D nonlinear map on
+    a 21^3 grid and 1D Poisson, 20 iterations against the oracle (which forms
+    c in a separate pass, as Alg. 2 writes it)."""
+    device()
+    aa = aa_mod()
+    for prob in (W.nonlinear3d(s=21, seed=6), W.poisson1d()):
+        iters = 20
+        xs_ref, st, _ = O.run_aa(lambda u: O.G_stencil(prob, u), np.zeros(prob.n), m, variant,
+                                 iters)
+        xs, ctx = gpu_aa_run(prob, m, variant, iters, flags=aa.FUSE_RHS, fused=False)
+        worst = max(rel(xs[i], xs_ref[i]) for i in range(1, iters + 2))
+        assert worst <= 1e-10, (prob.n, worst)
+        assert ctx.info().status == 0
+        _, _, rhs = ctx.sync_counts()
+        # the separate R gamma = Q^T f pass runs only for MGS and the first add
+        assert rhs == (iters if variant == "mgs" else 1), rhs
+
+
+@pytest.mark.parametrize("flags", [1 << 1, 1 << 4, (1 << 1) | (1 << 4)])
+def test_dcgs2_fused_rhs_readings_match_oracle(flags):
+    """DCGS-2's fused Q^T f corrects c_{k-1} for the reorthogonalized previous
+    column; both readings of Alg. 6 (A7, A8) against the oracle."""
+    device()
+    aa = aa_mod()
+    prob = W.nonlinear3d(s=21, seed=6)
+    iters = 20
+    xs_ref, _, _ = O.run_aa(lambda u: O.G_stencil(prob, u), np.zeros(prob.n), 6, "dcgs2", iters,
+                            flags=flags)
+    xs, ctx = gpu_aa_run(prob, 6, "dcgs2", iters, flags=flags | aa.FUSE_RHS, fused=False)
+    worst = max(rel(xs[i], xs_ref[i]) for i in range(1, iters + 2))
+    assert worst <= 1e-10, worst
+
+
+@pytest.mark.parametrize("variant", ["icwy", "cgs2", "dcgs2"])
+def test_aa_fused_rhs_full_size_matches_separate(variant):
+    """256^3, m = 20 (the benchmark configuration), 20 iterations: the fused
+    right-hand side against the separate pass on the GPU (the oracle route at
+    this size is covered for m = 5 above)."""
+    device()
+    aa = aa_mod()
+    prob = W.nonlinear3d()
+    a, _ = gpu_aa_run(prob, 20, variant, 20)
+    b, ctx = gpu_aa_run(prob, 20, variant, 20, flags=aa.FUSE_RHS)
+    assert ctx.info().status == 0
+    worst = max(rel(b[i], a[i]) for i in range(1, 22))
+    assert worst <= 1e-10, worst
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
 def test_aa_tiny_and_secant(variant):
     """n = 1, m = 1 (the secant case) and n = 7 (less than a wave)."""
     device()
