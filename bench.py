@@ -232,6 +232,47 @@ def batched_run(probs, ms, variant, tol, cap, chunk, stream, net=None, steady=20
     return out
 
 
+def poisson1d_to_tolerance(variant, tol=1e-8, cap=300, check_every=1):
+    """The 1D Poisson workload (n = 4096, m = 5) solved to ||f|| <= tol ||f_0||
+    with the single-instance entry points (the one-workgroup step at this n),
+    host stop test every step; the CPU oracle timed on the same solve."""
+    import numpy as np
+    import torch
+    import aa_workloads as W
+    import oracle as O
+    from paper_2110_09667_amd import aa
+    prob = W.poisson1d()
+    m = 5
+    f_d = torch.from_numpy(prob.f).cuda()
+    ctx = aa.AAContext(prob.n, m, variant)
+    x = torch.zeros(prob.n, dtype=torch.float64, device="cuda:0")
+    g = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it = 0
+    while it < cap:
+        aa.aa_problem_apply(prob.d, prob.s, prob.h, prob.omega, prob.c, f_d, x, g)
+        ctx.step(x, g, x)
+        it += 1
+        if it % check_every == 0:
+            info = ctx.info()
+            if info.iter > 1 and info.res_norm <= tol * info.res0_norm:
+                break
+    torch.cuda.synchronize()
+    gpu_s = time.perf_counter() - t0
+    info = ctx.info()
+    ctx.close()
+    if not os.path.exists(O.LIB_PATH):
+        O.build()
+    t0 = time.perf_counter()
+    _, st, res = O.run_aa(lambda u: O.G_stencil(prob, u), np.zeros(prob.n), m, variant, cap,
+                          tol=tol, record=False)
+    cpu_s = time.perf_counter() - t0
+    return {"iterations": it, "converged": bool(info.res_norm <= tol * info.res0_norm),
+            "gpu_ms": round(1e3 * gpu_s, 3), "us_per_iter": round(1e6 * gpu_s / max(it, 1), 1),
+            "oracle_iterations": len(res), "oracle_ms": round(1e3 * cpu_s, 3)}
+
+
 def one_at_a_time(probs, ms, variant, tol, cap, check_every=10):
     """The same instances solved one after another through the single-instance
     entry points (aa_problem_apply + aa_step on one context per instance),
@@ -306,6 +347,12 @@ def batched_suite(variant, count, cap, train_count, train_iters, sample, lr=1e-3
         learned = batched_run(probs, ms, variant, tol, cap, 50, stream, net=net)
         print(f"# batched learned: {learned['steady_ms_per_iter']:.2f} ms/iter, "
               f"{learned['wall_s']:.1f} s", file=sys.stderr, flush=True)
+        # ablation: the same guard with the untrained network (delta gamma = 0,
+        # beta = sigmoid(4)): what the training itself adds
+        net0 = aa.AAMlp(count, seed=1, stream=stream)
+        untrained = batched_run(probs, ms, variant, tol, cap, 50, stream, net=net0)
+        print(f"# batched guarded, untrained network: {untrained['wall_s']:.1f} s",
+              file=sys.stderr, flush=True)
     rng = np.random.default_rng(12345)
     pick = sorted(rng.choice(count, size=min(sample, count), replace=False).tolist())
     single = one_at_a_time([probs[j] for j in pick], [ms[j] for j in pick], variant, tol, cap)
@@ -323,7 +370,7 @@ def batched_suite(variant, count, cap, train_count, train_iters, sample, lr=1e-3
                 "g_evals_total": int(sum(s.g_evals for s in st)),
                 "accepted_total": int(sum(s.accepted for s in st))}
 
-    sp, sl = summary(plain), summary(learned)
+    sp, sl, su = summary(plain), summary(learned), summary(untrained)
     both = [j for j in range(count)
             if plain["states"][j].res_norm <= tol * plain["states"][j].res0_norm
             and learned["states"][j].res_norm <= tol * learned["states"][j].res0_norm]
@@ -339,6 +386,7 @@ def batched_suite(variant, count, cap, train_count, train_iters, sample, lr=1e-3
                     "train_final_mean_loss": float(np.mean([s.loss for s in tstates])),
                     "both_converged": len(both),
                     "median_iter_ratio_learned_over_plain": float(np.median(gi))},
+        "guarded_untrained_network": su,
         "one_at_a_time_sample": {
             "instances": len(pick), "seconds": round(t_single, 3),
             "converged": sum(1 for _, _, c in single if c),
@@ -445,7 +493,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched / learned-guarded / one-at-a-time comparison")
     ap.add_argument("--batch-count", type=int, default=4096)
-    ap.add_argument("--batch-cap", type=int, default=1000,
+    ap.add_argument("--batch-cap", type=int, default=600,
                     help="iteration cap of the batched time-to-tolerance runs")
     ap.add_argument("--train-count", type=int, default=4096)
     ap.add_argument("--train-iters", type=int, default=50)
@@ -501,6 +549,18 @@ def main():
             print(f"# {v}: {r['ms_per_step']:.3f} ms/step, {r['gbs']:.0f} GB/s",
                   file=sys.stderr, flush=True)
 
+    fused_rhs = {}
+    if not args.no_other_variants and args.rhs == "separate":
+        # the same steps with R gamma = Q^T f_i folded into the QRAdd passes
+        for v in VARIANTS:
+            r = run_variant(prob, args.m, v, max(5, args.steps // 2), 2, args.grid,
+                            profile=False, flags=aa.FUSE_RHS)
+            sep = main_res if v == args.variant else others[v]
+            fused_rhs[v] = {"ms_per_step": round(r["ms_per_step"], 4),
+                            "speedup_vs_separate": round(sep["ms_per_step"] / r["ms_per_step"], 3)}
+            print(f"# {v} with the RHS folded into QRAdd: {r['ms_per_step']:.3f} ms/step",
+                  file=sys.stderr, flush=True)
+
     qradd = {}
     if not args.no_qr_micro:
         # QRAdd / QRDelete alone: at the 3D workload's n with k = m - 1 (the
@@ -521,6 +581,14 @@ def main():
                                    for k, d in r.items()}
                 print(f"# qradd {label} {v}: " + ", ".join(
                     f"k={k} {d['add_gbs']:.0f}" for k, d in r.items()), file=sys.stderr, flush=True)
+
+    poisson = {}
+    if not args.no_other_variants:
+        for v in VARIANTS:
+            poisson[v] = poisson1d_to_tolerance(v)
+            print(f"# 1D Poisson n=4096 m=5 {v}: {poisson[v]['iterations']} iterations, "
+                  f"{poisson[v]['gpu_ms']:.1f} ms (oracle {poisson[v]['oracle_ms']:.1f} ms)",
+                  file=sys.stderr, flush=True)
 
     batched = None
     if not args.no_batch:
@@ -563,6 +631,8 @@ def main():
         "pct_hbm_peak": 100.0 * main_res["gbs"] / HBM_PEAK_GBS,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "poisson1d_to_1e-8": poisson,
+        "fused_rhs": fused_rhs,
         "qradd": qradd,
         "batched": batched,
         "per_variant": {v: {"ms_per_step": r["ms_per_step"], "gbs": r["gbs"],
