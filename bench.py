@@ -262,6 +262,18 @@ def poisson1d_to_tolerance(variant, tol=1e-8, cap=300, check_every=1):
     gpu_s = time.perf_counter() - t0
     info = ctx.info()
     ctx.close()
+    # the same solve through the batched entry points with one instance: the
+    # stop test runs on the device, one launch per iteration, one wait at the end
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = aa.AABatch([prob], [m], variant, tol=tol, max_iter=cap, stream=stream)
+        b.set_schedule(use_graph=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(cap + 1)
+        bst, _ = b.read()
+        batch_s = time.perf_counter() - t0
+        b.close()
     if not os.path.exists(O.LIB_PATH):
         O.build()
     t0 = time.perf_counter()
@@ -269,7 +281,10 @@ def poisson1d_to_tolerance(variant, tol=1e-8, cap=300, check_every=1):
                           tol=tol, record=False)
     cpu_s = time.perf_counter() - t0
     return {"iterations": it, "converged": bool(info.res_norm <= tol * info.res0_norm),
+            "final_rel_residual": info.res_norm / info.res0_norm,
             "gpu_ms": round(1e3 * gpu_s, 3), "us_per_iter": round(1e6 * gpu_s / max(it, 1), 1),
+            "batch_api_iterations": int(bst[0].stop_iter if not bst[0].active else bst[0].iter),
+            "batch_api_ms": round(1e3 * batch_s, 3),
             "oracle_iterations": len(res), "oracle_ms": round(1e3 * cpu_s, 3)}
 
 
@@ -499,6 +514,8 @@ def main():
     ap.add_argument("--train-iters", type=int, default=50)
     ap.add_argument("--single-sample", type=int, default=64,
                     help="instances run one at a time for the comparison")
+    ap.add_argument("--poisson-only", action="store_true",
+                    help="only the 1D Poisson time-to-tolerance measurement (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (5 times), to "
                          "calibrate the HBM byte counters of a profiler")
@@ -531,6 +548,11 @@ def main():
         __graft_entry__.build()
     aa.lib()
 
+    if args.poisson_only:
+        for v in VARIANTS:
+            print(json.dumps({v: poisson1d_to_tolerance(v)}), flush=True)
+        return
+
     prob = Problem3D(args.s)
     print(f"# workload: 3D nonlinear, s={args.s}, n={prob.n}, m={args.m}", file=sys.stderr,
           flush=True)
@@ -560,6 +582,15 @@ def main():
                             "speedup_vs_separate": round(sep["ms_per_step"] / r["ms_per_step"], 3)}
             print(f"# {v} with the RHS folded into QRAdd: {r['ms_per_step']:.3f} ms/step",
                   file=sys.stderr, flush=True)
+            if v != "mgs":
+                # also merging QRDelete's pass with the QRAdd's first
+                r2 = run_variant(prob, args.m, v, max(5, args.steps // 2), 2, args.grid,
+                                 profile=False, flags=aa.FUSE_RHS | aa.FUSE_DELETE)
+                fused_rhs[v]["with_fused_delete"] = {
+                    "ms_per_step": round(r2["ms_per_step"], 4),
+                    "speedup_vs_separate": round(sep["ms_per_step"] / r2["ms_per_step"], 3)}
+                print(f"# {v} with the RHS folded and QRDelete fused with QRAdd: "
+                      f"{r2['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
 
     qradd = {}
     if not args.no_qr_micro:
@@ -587,7 +618,8 @@ def main():
         for v in VARIANTS:
             poisson[v] = poisson1d_to_tolerance(v)
             print(f"# 1D Poisson n=4096 m=5 {v}: {poisson[v]['iterations']} iterations, "
-                  f"{poisson[v]['gpu_ms']:.1f} ms (oracle {poisson[v]['oracle_ms']:.1f} ms)",
+                  f"{poisson[v]['gpu_ms']:.1f} ms (one-instance batch: "
+                  f"{poisson[v]['batch_api_ms']:.1f} ms; oracle {poisson[v]['oracle_ms']:.1f} ms)",
                   file=sys.stderr, flush=True)
 
     batched = None

@@ -73,6 +73,14 @@ enum {
    * reduction per iteration.  MGS and the first QRAdd keep the separate
    * pass. */
   AA_FUSE_RHS = 1u << 3,
+  /* aa_step with ICWY once the window is full: QRDelete's rotation pass also
+   * stages Delta f (and f_i with AA_FUSE_RHS) beside the rotated columns, so
+   * the one matrix-core contraction that refreshes T (Sec. 3.2) also yields
+   * Q^T Delta f, the first reduction of the QRAdd that follows (Alg. 4).
+   * Same quantities, different rounding order; one pass over Q and one
+   * reduction fewer per iteration (ICWY: 2 instead of 3 with the delete).
+   * Windows up to 62 columns (63 without AA_FUSE_RHS). */
+  AA_FUSE_DELETE = 1u << 5,
   /* Workspace for the QR update only (aa_qr_add / aa_qr_delete /
    * aa_qr_solve); aa_step is then unavailable.  Saves (m + 3) n doubles. */
   AA_QR_ONLY = 1u << 8

@@ -18,6 +18,7 @@ VARIANTS = {"mgs": MGS, "cgs2": CGS2, "dcgs2": DCGS2, "icwy": ICWY}
 DCGS2_LITERAL = 1 << 1
 DCGS2_GUARD_GE3 = 1 << 4
 FUSE_RHS = 1 << 3
+FUSE_DELETE = 1 << 5
 QR_ONLY = 1 << 8
 MAX_COLS = 65
 

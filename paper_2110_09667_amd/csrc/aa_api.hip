@@ -180,9 +180,10 @@ Tail tail(int op, int k) {
 // the first pass adds Q^T f to its block dot products, the norm pass adds
 // w^T f (c_k = w^T f / R_kk); *rhs_done reports whether that happened.
 aa_status qr_add_impl(aa_ctx* c, const double* v, const double* f = nullptr,
-                      bool* rhs_done = nullptr) {
+                      bool* rhs_done = nullptr, bool first_done = false) {
   const int k = c->k;
   if (k >= c->cap) return AA_ESTATE;
+  if (first_done && (k == 0 || c->variant == AA_MGS)) return AA_EINVAL;
   const bool fuse = f != nullptr && k >= 1 && k + 1 <= 64 && c->variant != AA_MGS;
   if (rhs_done) *rhs_done = fuse;
   const int zf = fuse ? 1 : 0;  // one more vector read by each fused pass
@@ -233,8 +234,9 @@ aa_status qr_add_impl(aa_ctx* c, const double* v, const double* f = nullptr,
           d.z = f; d.nz = k;
           ts.rhs = 1; ts.zoff = k;
         }
-        chk(timed(c, AA_K_DOTS, k + 1 + zf,
-                  [&] { return launch_dots(d, c->sm, ts, G, st); }));
+        if (!first_done)
+          chk(timed(c, AA_K_DOTS, k + 1 + zf,
+                    [&] { return launch_dots(d, c->sm, ts, G, st); }));
         Cgs2bArgs b{c->Q, c->ldq, c->n, v, k, c->sm.coef0};
         const int Gb = grid_rows(c, c->grid_stream_max);
         chk(timed(c, AA_K_CGS2B, k + 1,
@@ -247,7 +249,7 @@ aa_status qr_add_impl(aa_ctx* c, const double* v, const double* f = nullptr,
           tn.rhs = 1;
         }
         chk(timed(c, AA_K_UPDATE, k + 2 + zf, [&] { return launch_update(uc, c->sm, tn, G, st); }));
-        c->syncs_add += 3;
+        c->syncs_add += first_done ? 2 : 3;
         break;
       }
       case AA_ICWY: {
@@ -259,8 +261,9 @@ aa_status qr_add_impl(aa_ctx* c, const double* v, const double* f = nullptr,
           d.z = f; d.nz = k;
           ti.rhs = 1; ti.zoff = 2 * k - 1;
         }
-        chk(timed(c, AA_K_DOTS, k + 1 + zf,
-                  [&] { return launch_dots(d, c->sm, ti, G, st); }));
+        if (!first_done)
+          chk(timed(c, AA_K_DOTS, k + 1 + zf,
+                    [&] { return launch_dots(d, c->sm, ti, G, st); }));
         UpdArgs ub = u;
         ub.v = v; ub.out = slotk; ub.j0 = 0; ub.nc = k; ub.c1 = c->sm.coef0; ub.nrm = 1;
         if (fuse) {
@@ -268,7 +271,7 @@ aa_status qr_add_impl(aa_ctx* c, const double* v, const double* f = nullptr,
           tn.rhs = 1;
         }
         chk(timed(c, AA_K_UPDATE, k + 2 + zf, [&] { return launch_update(ub, c->sm, tn, G, st); }));
-        c->syncs_add += 2;
+        c->syncs_add += first_done ? 1 : 2;
         break;
       }
       case AA_DCGS2: {
@@ -284,7 +287,8 @@ aa_status qr_add_impl(aa_ctx* c, const double* v, const double* f = nullptr,
           d.z = f; d.nz = k;
           ta.rhs = 1; ta.zoff = k + d.ny;
         }
-        chk(timed(c, AA_K_DOTS, k + 1 + zf, [&] { return launch_dots(d, c->sm, ta, G, st); }));
+        if (!first_done)
+          chk(timed(c, AA_K_DOTS, k + 1 + zf, [&] { return launch_dots(d, c->sm, ta, G, st); }));
         UpdArgs ub = u;
         ub.v = v; ub.out = slotk; ub.c1 = Rcol; ub.nrm = 1;
         if (fuse) {
@@ -298,7 +302,7 @@ aa_status qr_add_impl(aa_ctx* c, const double* v, const double* f = nullptr,
         }
         chk(timed(c, AA_K_UPDATE, k + (reorth ? 3 : 2) + zf,
                   [&] { return launch_update(ub, c->sm, tn, G, st); }));
-        c->syncs_add += 2;
+        c->syncs_add += first_done ? 1 : 2;
         break;
       }
       default:
@@ -336,6 +340,64 @@ aa_status qr_delete_impl(aa_ctx* c) {
   if (gram) c->syncs_del += 1;
   c->k = k - 1;
   return AA_OK;
+}
+
+// The tail of the QRAdd's first pass (block dot products) for the variant
+// with k columns present, as qr_add_impl builds it, and where its inputs sit
+// in that pass's reduced values: Q^T v at 0, the Gram row of q_{k-1}
+// (ICWY; DCGS-2 when it reorthogonalizes) at k, Q^T f after them.
+Tail first_pass_tail(const aa_ctx* c, int k, bool rhs) {
+  Tail t{};
+  t.k = k;
+  switch (c->variant) {
+    case AA_CGS2:
+      t.op = TAIL_CGS2_S;
+      t.zoff = k;
+      break;
+    case AA_ICWY:
+      t.op = TAIL_ICWY;
+      t.zoff = 2 * k - 1;
+      break;
+    default: {  // DCGS-2
+      const int m_i = k + 1;
+      t.op = TAIL_DCGS2;
+      t.reorth = (c->flags & AA_DCGS2_GUARD_GE3) ? (m_i >= 3) : (m_i > 3);
+      t.literal = (c->flags & AA_DCGS2_LITERAL) ? 1 : 0;
+      t.zoff = k + (t.reorth ? k - 1 : 0);
+    }
+  }
+  t.rhs = rhs ? 1 : 0;
+  return t;
+}
+
+// A full window with CGS-2, DCGS-2 or ICWY (AA_FUSE_DELETE): QRDelete's
+// rotation pass also stages v (and f) beside the rotated columns, and the
+// Gram of [Q v f] on the matrix cores yields at once ICWY's T refresh and
+// every block dot product the QRAdd's first pass would compute (Q^T v, the
+// Gram row of the last column, Q^T f).  The finalize rearranges them into
+// that pass's layout and runs its tail; qr_add_impl then continues from the
+// second pass.  One pass over Q and one reduction fewer per iteration.
+aa_status fused_delete_add(aa_ctx* c, const double* v, const double* f, bool* rhs_done) {
+  const int k = c->k, kk = k - 1;
+  const int naug = f ? 2 : 1;
+  const hipStream_t st = c->stream;
+  hipError_t e = timed(c, AA_K_GIVENS, 0, [&] { return launch_givens(c->sm, k, st); });
+  if (e != hipSuccess) return AA_EHIP;
+  RotArgs r{c->Q, c->ldq, c->n, k, c->sm.givens, 1, v, f, naug};
+  const int na = kk + naug;
+  const int64_t pairs = (int64_t)na * (na - 1) / 2;
+  const int64_t cap = pairs > 0 ? (int64_t)kPartials / pairs : c->grid_gram_max;
+  const int gmax = (int)(c->grid_gram_max < cap ? c->grid_gram_max : cap);
+  Tail tg = first_pass_tail(c, kk, f != nullptr);
+  tg.inner = tg.op;
+  tg.op = TAIL_GRAM_ADD;
+  tg.gram_t = c->variant == AA_ICWY ? 1 : 0;
+  e = timed(c, AA_K_ROTATE, 2 * k - 1 + naug,
+            [&] { return launch_rotate(r, c->sm, tg, grid_rows(c, gmax), st); });
+  if (e != hipSuccess) return AA_EHIP;
+  c->syncs_del += 1;
+  c->k = kk;
+  return qr_add_impl(c, v, f, rhs_done, true);
 }
 
 aa_status rhs_impl(aa_ctx* c, const double* f) {
@@ -386,26 +448,44 @@ aa_status fused_step(aa_ctx* c, const double* x, const double* g, double* x_next
   a.ov_iter = c->iter;
   a.ov_k = c->k;
   const int kb = c->m <= 8 ? 8 : c->m <= 16 ? 16 : c->m <= 32 ? 32 : 64;
-  const bool gram = c->variant == AA_ICWY;
+  const bool gram = batch_needs_gram(c->variant, c->flags);
   // model bytes and reduction counts of this iteration
   double vecs = 5;
   const int64_t i = c->iter;
   int k = c->k;
   if (i > 0) {
+    // the same decisions as the one-workgroup kernel (aa_batch.hip wg_front)
     const int m_i = (int)(i < c->m ? i : c->m);
+    const bool fold = (c->flags & AA_FUSE_RHS) && c->variant != AA_MGS && c->m + 1 <= 64;
+    const int kg = kb < 16 ? 16 : kb;
+    bool del_fused = false;
     vecs = 8;
     if (i > c->m) {
-      vecs += 2.0 * k - 1;
-      if (gram && k > 1) c->syncs_del += 1;
+      del_fused = (c->flags & AA_FUSE_DELETE) && c->variant != AA_MGS && k >= 2 &&
+                  k - 1 + (fold ? 2 : 1) <= kg;
+      vecs += 2.0 * k - 1 + (del_fused ? (fold ? 2 : 1) : 0);
+      if ((c->variant == AA_ICWY && k > 1) || del_fused) c->syncs_del += 1;
       k -= 1;
     }
-    vecs += add_vectors(c->variant, c->flags, k);
-    c->syncs_add += add_syncs(c->variant, k);
-    vecs += (k + 1) + (m_i + 3);
-    c->syncs_rhs += 1;
+    double add = add_vectors(c->variant, c->flags, k);
+    int64_t asy = add_syncs(c->variant, k);
+    if (del_fused) {  // the first pass's block dot products came with the rotation
+      add -= k + 1;
+      asy -= 1;
+    }
+    const bool rhs_folded = fold && k >= 1;
+    if (rhs_folded) add += del_fused ? 1 : 2;  // f in the first (unless fused) and norm passes
+    vecs += add;
+    c->syncs_add += asy;
+    if (!rhs_folded) {
+      vecs += k + 2;  // Q^T f_i over the k + 1 columns after the add
+      c->syncs_rhs += 1;
+    }
+    vecs += m_i + 3;
   }
   hipError_t e = timed(c, AA_K_FUSED, vecs,
-                       [&] { return launch_batch(a, 1, kb, gram, c->stream); });
+                       [&] { return launch_batch(a, 1, kb, gram, batch_stage_cols(c->m, c->variant, c->flags),
+                                           c->stream); });
   if (e != hipSuccess) return AA_EHIP;
   if (i == 0) {
     c->iter = 1;
@@ -525,10 +605,17 @@ aa_status aa_step(aa_ctx* c, const double* x, const double* g, double* x_next) {
             [&] { return launch_history(h, c->sm, tail(TAIL_RES, 0), G, st); }) != hipSuccess)
     return AA_EHIP;
   aa_status s = AA_OK;
-  if (i > m) s = qr_delete_impl(c);        // Alg. 2: QRDelete when the window is full
   bool rhs_done = false;
-  if (s == AA_OK)  // Alg. 2: QRAdd of Delta f_{i-1} (optionally also solving R gamma = Q^T f_i)
-    s = qr_add_impl(c, c->W, (c->flags & AA_FUSE_RHS) ? c->f_prev : nullptr, &rhs_done);
+  const bool fuse_rhs = (c->flags & AA_FUSE_RHS) != 0;
+  if (i > m && c->variant != AA_MGS && (c->flags & AA_FUSE_DELETE) && c->k >= 2 &&
+      c->k - 1 + (fuse_rhs ? 2 : 1) <= 64) {
+    // QRDelete + QRAdd of Delta f_{i-1} with their first reductions merged
+    s = fused_delete_add(c, c->W, fuse_rhs ? c->f_prev : nullptr, &rhs_done);
+  } else {
+    if (i > m) s = qr_delete_impl(c);  // Alg. 2: QRDelete when the window is full
+    if (s == AA_OK)  // Alg. 2: QRAdd of Delta f_{i-1} (optionally also R gamma = Q^T f_i)
+      s = qr_add_impl(c, c->W, fuse_rhs ? c->f_prev : nullptr, &rhs_done);
+  }
   if (s == AA_OK && !rhs_done) s = rhs_impl(c, c->f_prev);  // R gamma = Q^T f_i
   if (s != AA_OK) return s;
   XupdArgs xa{c->ring, c->ldq, m, (int)((i - m_i) % m), m_i, g, x, x_next, c->n, c->sm.gamma};

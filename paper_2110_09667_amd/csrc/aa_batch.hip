@@ -29,21 +29,22 @@ __device__ __forceinline__ Tail mk_tail(int op, int k) {
 template <int KB, bool GRAM>
 struct BatchLds {
   static constexpr int KG = KB < 16 ? 16 : KB;          // Gram block bucket
-  static constexpr int NACC = 2 * KB + 4;                // per-wave accumulators
+  static constexpr int NACC = 3 * KB + 4;                // per-wave accumulators
   static constexpr int NPG = GRAM ? GramShape<KG>::NP : 1;
   static constexpr int NRED = NACC > NPG ? NACC : NPG;
-  static constexpr int NSTAGE = GRAM ? GramShape<KG>::STAGE : 1;
   double acc[kWaves * NACC];
   double red[NRED];
   double c1[kMaxCols], c2[kMaxCols], cs[kMaxCols];
   double gc[KG], gs[KG];
   double sg[kMaxCols];
   int sslot[kMaxCols];
-  union {                 // the Givens scratch is dead once the rotations exist
-    double H[KB * KB];
-    double stage[NSTAGE];
-  };
 };
+
+// Dynamic LDS of the batched kernel: the Givens scratch (KB x KB), which is
+// dead once the rotations exist, then (ICWY) the Gram staging of the rotated
+// rows, sized on the host for the largest window of the batch
+// (max(KB^2, gram_lds_doubles(m_max - 1)) doubles).
+extern __shared__ double batch_dyn[];
 
 // Zero the accumulators, run body(this wave's accumulators), combine the
 // waves into red[0:nred], run the dense tail.  All threads call.
@@ -74,11 +75,15 @@ __device__ __forceinline__ void wg_scale(const Small& sm, int k, const double* i
   __syncthreads();
 }
 
-// QRAdd (Alg. 2 with Algs. 3-6) of v as column k; k columns present.
+// QRAdd (Alg. 2 with Algs. 3-6) of v as column k; k columns present.  With
+// f (not MGS, k >= 1) the passes also form c = Q^T f and the norm pass's tail
+// solves R gamma = c (as AA_FUSE_RHS on the grid path).  first_done: the
+// first pass's reduction and tail already ran (fused with QRDelete).
 template <int KB, class L>
 __device__ void wg_qr_add(const BInst& I, int variant, unsigned flags, int k, const double* v,
-                          L& lds) {
+                          L& lds, const double* f = nullptr, bool first_done = false) {
   const Small& sm = I.sm;
+  const bool fuse = f != nullptr && k >= 1 && variant != AA_MGS;
   double* slotk = I.Q + (int64_t)k * I.ld;
   double* Rcol = sm.R + (size_t)k * sm.cap;
   DotsArgs d{I.Q, I.ld, I.n, v, 0, nullptr, 0, 0};
@@ -87,14 +92,20 @@ __device__ void wg_qr_add(const BInst& I, int variant, unsigned flags, int k, co
   Tail tn = mk_tail(TAIL_NORM, k);
   tn.idx = 0;
   auto dots = [&](const DotsArgs& a, const Tail& t) {
-    wg_pass(sm, t, a.nx + a.ny + (a.xx ? 1 : 0), lds,
+    if (first_done) return;
+    wg_pass(sm, t, a.nx + a.ny + a.nz + (a.xx ? 1 : 0), lds,
             [&](double* acc) { dots_body(a, 0, 1, acc); });
   };
   auto update = [&](const UpdArgs& a, const Tail& t) {
     update_coefs(a, lds.c1, lds.c2, lds.cs);
-    wg_pass(sm, t, (a.dotcol >= 0 ? 1 : 0) + (a.nrm ? 1 : 0), lds,
+    wg_pass(sm, t, update_nred(a), lds,
             [&](double* acc) { update_body(a, lds.c1, lds.c2, lds.cs, 0, 1, acc); });
   };
+  if (fuse) {
+    tn.rhs = 1;
+    d.z = f;
+    d.nz = k;
+  }
   if (k == 0) {
     d.xx = 1;
     dots(d, tn);
@@ -123,7 +134,10 @@ __device__ void wg_qr_add(const BInst& I, int variant, unsigned flags, int k, co
     }
     case AA_CGS2: {
       d.nx = k;
-      dots(d, mk_tail(TAIL_CGS2_S, k));
+      Tail ts = mk_tail(TAIL_CGS2_S, k);
+      ts.rhs = fuse ? 1 : 0;
+      ts.zoff = k;
+      dots(d, ts);
       for (int j = threadIdx.x; j < KB; j += kWG) lds.cs[j] = (j < k) ? sm.coef0[j] : 0.0;
       Cgs2bArgs b{I.Q, I.ld, I.n, v, k, sm.coef0};
       wg_pass(sm, mk_tail(TAIL_CGS2_Z, k), k, lds,
@@ -131,6 +145,7 @@ __device__ void wg_qr_add(const BInst& I, int variant, unsigned flags, int k, co
       UpdArgs uc = u;
       uc.v = v; uc.out = slotk; uc.j0 = 0; uc.nc = k; uc.c1 = sm.coef0; uc.c2 = sm.coef1;
       uc.nrm = 1;
+      uc.rhsv = fuse ? f : nullptr;
       update(uc, tn);
       break;
     }
@@ -138,9 +153,13 @@ __device__ void wg_qr_add(const BInst& I, int variant, unsigned flags, int k, co
       d.nx = k;
       d.y = I.Q + (int64_t)(k - 1) * I.ld;
       d.ny = k - 1;
-      dots(d, mk_tail(TAIL_ICWY, k));
+      Tail ti = mk_tail(TAIL_ICWY, k);
+      ti.rhs = fuse ? 1 : 0;
+      ti.zoff = 2 * k - 1;
+      dots(d, ti);
       UpdArgs ub = u;
       ub.v = v; ub.out = slotk; ub.j0 = 0; ub.nc = k; ub.c1 = sm.coef0; ub.nrm = 1;
+      ub.rhsv = fuse ? f : nullptr;
       update(ub, tn);
       break;
     }
@@ -153,9 +172,12 @@ __device__ void wg_qr_add(const BInst& I, int variant, unsigned flags, int k, co
       Tail ta = mk_tail(TAIL_DCGS2, k);
       ta.reorth = reorth;
       ta.literal = (flags & AA_DCGS2_LITERAL) ? 1 : 0;
+      ta.rhs = fuse ? 1 : 0;
+      ta.zoff = k + d.ny;
       dots(d, ta);
       UpdArgs ub = u;
       ub.v = v; ub.out = slotk; ub.c1 = Rcol; ub.nrm = 1;
+      ub.rhsv = fuse ? f : nullptr;
       if (reorth) {
         ub.dcgs2_p = k - 1; ub.reorth = 1; ub.s = sm.coef1; ub.j0 = 0; ub.nc = k - 1;
       } else {
@@ -174,7 +196,7 @@ template <int KB, bool GRAM, class L>
 __device__ void wg_qr_delete(const BInst& I, int variant, int k, L& lds) {
   const Small& sm = I.sm;
   if (k <= 1) return;
-  givens_body(sm, k, lds.H);
+  givens_body(sm, k, batch_dyn);
   __syncthreads();
   RotArgs r{I.Q, I.ld, I.n, k, sm.givens, 0};
   givens_coefs(r, sm.cap, lds.gc, lds.gs, L::KG);
@@ -183,16 +205,16 @@ __device__ void wg_qr_delete(const BInst& I, int variant, int k, L& lds) {
     if (variant == AA_ICWY) {
       constexpr int KG = L::KG;
       using S = GramShape<KG>;
-      v4d acc[S::NBP];
-      rotate_gram_body<KG>(r, lds.gc, lds.gs, 0, 1, lds.stage, S::KP, acc);
-      __syncthreads();
-      gram_store<KG>(acc, lds.stage + (threadIdx.x >> 6) * S::NP, k - 1);
-      __syncthreads();
       const int kk = k - 1, nred = kk * (kk - 1) / 2;
+      v4d acc[S::NBP];
+      rotate_gram_body<KG>(r, lds.gc, lds.gs, 0, 1, batch_dyn, gram_stride(kk), acc);
+      __syncthreads();
+      gram_store<KG>(acc, batch_dyn + (threadIdx.x >> 6) * nred, kk);
+      __syncthreads();
       for (int c = threadIdx.x; c < nred; c += kWG) {
-        double s = lds.stage[c];
+        double s = batch_dyn[c];
 #pragma unroll
-        for (int w = 1; w < kWaves; ++w) s += lds.stage[w * S::NP + c];
+        for (int w = 1; w < kWaves; ++w) s += batch_dyn[w * nred + c];
         lds.red[c] = s;
       }
       __syncthreads();
@@ -203,6 +225,84 @@ __device__ void wg_qr_delete(const BInst& I, int variant, int k, L& lds) {
   }
   rotate_body(r, lds.gc, lds.gs, 0, 1);
   __syncthreads();
+}
+
+// Whether QRDelete with k columns can share its pass with the QRAdd's first
+// (AA_FUSE_DELETE, not MGS; the staged [Q v (f)] must fit the Gram bucket).
+template <bool GRAM, class L>
+__device__ __forceinline__ bool delete_fusable(const BatchArgs& b, int k, bool rhs) {
+  if constexpr (!GRAM) {
+    return false;
+  } else {
+    return (b.flags & AA_FUSE_DELETE) && b.variant != AA_MGS && k >= 2 &&
+           k - 1 + (rhs ? 2 : 1) <= L::KG;
+  }
+}
+
+// QRDelete fused with the first pass of the QRAdd of v (AA_FUSE_DELETE): the
+// rotation stages v (and f) beside the rotated rows, one Gram of [Q v (f)]
+// on the matrix cores gives ICWY's T refresh and every block dot product of
+// the QRAdd's first pass; they are laid out as that pass would have reduced
+// them and its tail runs.  k columns present on entry (k - 1 after).
+template <int KB, bool GRAM, class L>
+__device__ void wg_delete_first_pass(const BInst& I, int variant, unsigned flags, int k,
+                                     const double* v, const double* f, L& lds) {
+  if constexpr (GRAM) {
+    const Small& sm = I.sm;
+    givens_body(sm, k, batch_dyn);
+    __syncthreads();
+    const int naug = f ? 2 : 1;
+    RotArgs r{I.Q, I.ld, I.n, k, sm.givens, 1, v, f, naug};
+    givens_coefs(r, sm.cap, lds.gc, lds.gs, L::KG);
+    __syncthreads();
+    constexpr int KG = L::KG;
+    using S = GramShape<KG>;
+    const int kk = k - 1, na = kk + naug, np = na * (na - 1) / 2;
+    v4d acc[S::NBP];
+    rotate_gram_body<KG>(r, lds.gc, lds.gs, 0, 1, batch_dyn, gram_stride(na), acc);
+    __syncthreads();
+    gram_store<KG>(acc, batch_dyn + (threadIdx.x >> 6) * np, na);
+    __syncthreads();
+    for (int c = threadIdx.x; c < np; c += kWG) {
+      double s = batch_dyn[c];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) s += batch_dyn[w * np + c];
+      lds.red[c] = s;
+    }
+    __syncthreads();
+    if (variant == AA_ICWY) {
+      run_tail(sm, mk_tail(TAIL_GRAM, kk), lds.red);
+      __syncthreads();
+    }
+    // the first pass's tail and layout for kk columns (as wg_qr_add builds them)
+    Tail t = mk_tail(TAIL_ICWY, kk);
+    t.rhs = f ? 1 : 0;
+    bool row = true;
+    if (variant == AA_CGS2) {
+      t.op = TAIL_CGS2_S;
+      t.zoff = kk;
+      row = false;
+    } else if (variant == AA_ICWY) {
+      t.zoff = 2 * kk - 1;
+    } else {
+      const int m_i = kk + 1;
+      t.op = TAIL_DCGS2;
+      t.reorth = (flags & AA_DCGS2_GUARD_GE3) ? (m_i >= 3) : (m_i > 3);
+      t.literal = (flags & AA_DCGS2_LITERAL) ? 1 : 0;
+      t.zoff = kk + (t.reorth ? kk - 1 : 0);
+      row = t.reorth != 0;
+    }
+    const int pv = kk * (kk - 1) / 2, pf = (kk + 1) * kk / 2, prow = (kk - 1) * (kk - 2) / 2;
+    double* red2 = lds.acc;  // free between passes
+    for (int b2 = threadIdx.x; b2 < kk; b2 += kWG) {
+      red2[b2] = lds.red[pv + b2];
+      if (row && b2 < kk - 1) red2[kk + b2] = lds.red[prow + b2];
+      if (f) red2[t.zoff + b2] = lds.red[pf + b2];
+    }
+    __syncthreads();
+    run_tail(sm, t, red2);
+    __syncthreads();
+  }
 }
 
 // Front of one iteration of Alg. 1 for one instance (every thread of the
@@ -246,14 +346,28 @@ __device__ bool wg_front(const BatchArgs& b, const BInst& I, BState& st, L& lds,
     return false;
   }
   int k = st.k;
+  // AA_FUSE_RHS: c = Q^T f_i inside the QRAdd passes (not MGS, not the first add)
+  const double* fr =
+      ((b.flags & AA_FUSE_RHS) && b.variant != AA_MGS && I.m + 1 <= 64) ? I.f_prev : nullptr;
+  const bool rhs_folded = fr != nullptr && (it > m ? k - 1 : k) >= 1;
   if (it > m) {
-    wg_qr_delete<KB, GRAM>(I, b.variant, k, lds);
-    k -= 1;
+    if (delete_fusable<GRAM, L>(b, k, fr != nullptr)) {
+      wg_delete_first_pass<KB, GRAM>(I, b.variant, b.flags, k, I.W, fr, lds);
+      k -= 1;
+      wg_qr_add<KB>(I, b.variant, b.flags, k, I.W, lds, fr, true);
+    } else {
+      wg_qr_delete<KB, GRAM>(I, b.variant, k, lds);
+      k -= 1;
+      wg_qr_add<KB>(I, b.variant, b.flags, k, I.W, lds, fr);
+    }
+  } else {
+    wg_qr_add<KB>(I, b.variant, b.flags, k, I.W, lds, fr);
   }
-  wg_qr_add<KB>(I, b.variant, b.flags, k, I.W, lds);
   k += 1;
-  DotsArgs d{I.Q, I.ld, I.n, I.f_prev, k, nullptr, 0, 0};
-  wg_pass(sm, mk_tail(TAIL_RHS, k), k, lds, [&](double* acc) { dots_body(d, 0, 1, acc); });
+  if (!rhs_folded) {
+    DotsArgs d{I.Q, I.ld, I.n, I.f_prev, k, nullptr, 0, 0};
+    wg_pass(sm, mk_tail(TAIL_RHS, k), k, lds, [&](double* acc) { dots_body(d, 0, 1, acc); });
+  }
   st.k = k;
   st.m_i = m_i;
   st.status = *sm.status;
@@ -546,20 +660,41 @@ __global__ void k_batch_init(BInst* inst, int count) {
 }
 
 template <bool GRAM>
-static hipError_t launch_kb(const BatchArgs& b, int grid, int kb, hipStream_t st) {
+static hipError_t launch_kb(const BatchArgs& b, int grid, int kb, size_t lds, hipStream_t st) {
   switch (kb) {
-    case 8: hipLaunchKernelGGL((k_batch<8, GRAM>), dim3(grid), dim3(kWG), 0, st, b); break;
-    case 16: hipLaunchKernelGGL((k_batch<16, GRAM>), dim3(grid), dim3(kWG), 0, st, b); break;
-    case 32: hipLaunchKernelGGL((k_batch<32, GRAM>), dim3(grid), dim3(kWG), 0, st, b); break;
-    case 64: hipLaunchKernelGGL((k_batch<64, GRAM>), dim3(grid), dim3(kWG), 0, st, b); break;
+    case 8: hipLaunchKernelGGL((k_batch<8, GRAM>), dim3(grid), dim3(kWG), lds, st, b); break;
+    case 16: hipLaunchKernelGGL((k_batch<16, GRAM>), dim3(grid), dim3(kWG), lds, st, b); break;
+    case 32: hipLaunchKernelGGL((k_batch<32, GRAM>), dim3(grid), dim3(kWG), lds, st, b); break;
+    case 64: hipLaunchKernelGGL((k_batch<64, GRAM>), dim3(grid), dim3(kWG), lds, st, b); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchArgs& b, int grid, int kbucket, bool gram, hipStream_t st) {
+hipError_t launch_batch(const BatchArgs& b, int grid, int kbucket, bool gram, int stage_cols,
+                        hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
-  return gram ? launch_kb<true>(b, grid, kbucket, st) : launch_kb<false>(b, grid, kbucket, st);
+  if (stage_cols < 0 || stage_cols > (kbucket < 16 ? 16 : kbucket)) return hipErrorInvalidValue;
+  int dyn = kbucket * kbucket;
+  if (gram && stage_cols > 0 && gram_lds_doubles(stage_cols) > dyn)
+    dyn = gram_lds_doubles(stage_cols);
+  const size_t lds = sizeof(double) * (size_t)dyn;
+  return gram ? launch_kb<true>(b, grid, kbucket, lds, st)
+              : launch_kb<false>(b, grid, kbucket, lds, st);
+}
+
+bool batch_needs_gram(int variant, unsigned flags) {
+  return variant == AA_ICWY || ((flags & AA_FUSE_DELETE) && variant != AA_MGS);
+}
+
+int batch_stage_cols(int mmax, int variant, unsigned flags) {
+  if (!batch_needs_gram(variant, flags) || mmax < 2) return 0;
+  int cols = mmax - 1;
+  if ((flags & AA_FUSE_DELETE) && variant != AA_MGS)
+    cols += ((flags & AA_FUSE_RHS) ? 2 : 1);
+  const int kb = mmax <= 8 ? 8 : mmax <= 16 ? 16 : mmax <= 32 ? 32 : 64;
+  const int kg = kb < 16 ? 16 : kb;
+  return cols < kg ? cols : kg;  // wider windows fall back to the separate passes
 }
 
 hipError_t launch_batch_init(BInst* inst, int count, hipStream_t st) {

@@ -32,6 +32,7 @@ struct aa_batch {
   std::vector<int> m;
   std::vector<int> dim;
   int kbucket = 8;
+  int mmax = 1;         // largest window of the batch
   bool gram = false;
   int grid = 0;        // persistent workgroups (0: 2 per compute unit)
   int order_mode = 0;  // 0: largest n*m first, 1: as given
@@ -108,7 +109,8 @@ hipError_t enqueue_mode(aa_batch* b, int mode, float dscale) {
   if (grid > b->count) grid = b->count;
   hipError_t e = launch_batch_reset(b->d_counter, b->stream);
   if (e != hipSuccess) return e;
-  return launch_batch(a, grid, b->kbucket, b->gram, b->stream);
+  return launch_batch(a, grid, b->kbucket, b->gram,
+                      batch_stage_cols(b->mmax, b->variant, b->flags), b->stream);
 }
 
 hipError_t enqueue(aa_batch* b, int iters) {
@@ -220,7 +222,8 @@ aa_status aa_batch_init(aa_batch** out, int count, const aa_batch_instance* inst
     mmax = std::max(mmax, m);
   }
   b->kbucket = bucket(mmax);
-  b->gram = variant == AA_ICWY;
+  b->mmax = mmax;
+  b->gram = batch_needs_gram(variant, flags);
   hipError_t e = hipMemcpyAsync(b->d_inst, hi.data(), sizeof(BInst) * count,
                                 hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess)

@@ -55,8 +55,17 @@ __device__ __forceinline__ double multi_reduce(double (&v)[N]) {
 // them streaming measurably raises the sustained read bandwidth.
 // ---------------------------------------------------------------------------
 
+// AA_STREAMING (default 1): the passes stream data far larger than the
+// caches, so full tiles use non-temporal loads and the rotation sweep
+// non-temporal stores.  (Measured also for the batched kernel, whose 4096
+// instances together far exceed the caches: 36.4 ms per iteration with them,
+// 37.2 ms with ordinary loads and stores.)  Defining it to 0 before including
+// this header restores ordinary accesses.
+#ifndef AA_STREAMING
+#define AA_STREAMING 1
+#endif
 #ifndef AA_NT_LOAD
-#define AA_NT_LOAD 1
+#define AA_NT_LOAD AA_STREAMING
 #endif
 #ifndef AA_NT_STORE
 #define AA_NT_STORE 0
@@ -80,7 +89,20 @@ __device__ __forceinline__ f64x2 ld2v(const double2* p) {
 // Store one 16-byte pair that no later pass of this call reads back soon
 // (non-temporal: the written columns far exceed the caches).
 __device__ __forceinline__ void st2v_stream(f64x2 v, double* p) {
+#if AA_STREAMING
   __builtin_nontemporal_store(v, reinterpret_cast<f64x2*>(p));
+#else
+  *reinterpret_cast<f64x2*>(p) = v;
+#endif
+}
+
+// Store one streamed value (the row-per-thread rotation sweep).
+__device__ __forceinline__ void st1_stream(double v, double* p) {
+#if AA_STREAMING
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
 }
 
 // One streamed value (the row-per-thread sweeps).

@@ -39,7 +39,9 @@ enum TailOp : int {
   TAIL_RES,       // scal[S_RES] = red[0]
   TAIL_FIRST,     // scal[S_RES0] = scal[S_RES] = red[0], scal[S_STEP] = red[1]
   TAIL_STEP,      // scal[S_STEP] = red[0]
-  TAIL_GRAM       // T strict lower from pair sums
+  TAIL_GRAM,      // T strict lower from pair sums
+  TAIL_GRAM_ADD   // pairs of [Q v (f)]: T refresh (gram_t), then the QRAdd's
+                  // first-pass tail `inner` on the rearranged values (finalize)
 };
 
 // Device-resident small dense state (pointers into the workspace).
@@ -66,6 +68,8 @@ struct Tail {
   int literal;  // TAIL_DCGS2
   int rhs;      // R gamma = Q^T f folded into the QRAdd passes (see aa_step)
   int zoff;     // first QRAdd pass with rhs: index of Q^T f in red[]
+  int inner;    // TAIL_GRAM_ADD: the QRAdd first-pass tail to run afterwards
+  int gram_t;   // TAIL_GRAM_ADD: also refresh T from the Gram (ICWY)
 };
 
 // ---- streaming passes -------------------------------------------------------
@@ -111,6 +115,9 @@ struct RotArgs {         // Givens sweep over k columns (+ ICWY Gram of k-1)
   double* Q; int64_t ldq; int64_t n; int k;
   const double* givens;
   int gram;
+  // Gram only: naug vectors appended after the k-1 rotated columns (v, then
+  // f), so the same contraction also yields Q^T v and Q^T f
+  const double* v; const double* f; int naug;
 };
 
 struct ScaleArgs { const double* in; double* out; int64_t n; const double* R; int kk; int cap; };
@@ -185,7 +192,14 @@ struct BatchArgs {
   float dscale;           // scale of dout (1 / count)
 };
 
-hipError_t launch_batch(const BatchArgs&, int grid, int kbucket, bool gram, hipStream_t);
+// stage_cols: largest number of columns the Gram staging holds (0: none);
+// dynamic LDS = max(kbucket^2, gram_lds_doubles(stage_cols)) doubles.
+hipError_t launch_batch(const BatchArgs&, int grid, int kbucket, bool gram, int stage_cols,
+                        hipStream_t);
+// Staged Gram columns and whether the batched kernel needs its Gram
+// instantiation, for a window of up to mmax columns, variant and flags.
+int batch_stage_cols(int mmax, int variant, unsigned flags);
+bool batch_needs_gram(int variant, unsigned flags);
 hipStream_t mlp_stream(const aa_mlp*);
 int mlp_max_batch(const aa_mlp*);
 hipError_t launch_batch_reset(unsigned* counter, hipStream_t);

@@ -62,7 +62,32 @@ __global__ __launch_bounds__(kFinWG) void k_finalize(Small sm, Tail t, int nred,
     }
   }
   __syncthreads();
-  run_tail(sm, t, red);
+  if (t.op != TAIL_GRAM_ADD) {
+    run_tail(sm, t, red);
+    return;
+  }
+  // QRDelete fused with the QRAdd's first pass: red holds the Gram pairs of
+  // [q_0 .. q_{k-1}, v, (f)] (pair a(a-1)/2 + b, b < a).  Refresh T (ICWY),
+  // then lay out what the first pass would have reduced -- Q^T v, the Gram
+  // row of q_{k-1} where the variant uses it, Q^T f -- and run its tail.
+  __shared__ double red2[kMaxRed];
+  const int k = t.k;
+  if (t.gram_t) {
+    Tail tg = t;
+    tg.op = TAIL_GRAM;
+    run_tail(sm, tg, red);
+  }
+  const int pv = k * (k - 1) / 2, pf = (k + 1) * k / 2, prow = (k - 1) * (k - 2) / 2;
+  const bool row = t.inner == TAIL_ICWY || (t.inner == TAIL_DCGS2 && t.reorth);
+  for (int b = threadIdx.x; b < k; b += kFinWG) {
+    red2[b] = red[pv + b];
+    if (row && b < k - 1) red2[k + b] = red[prow + b];
+    if (t.rhs) red2[t.zoff + b] = red[pf + b];
+  }
+  __syncthreads();
+  Tail ti = t;
+  ti.op = t.inner;
+  run_tail(sm, ti, red2);
 }
 
 __global__ __launch_bounds__(kWG) void k_dots(DotsArgs a, Small sm) {
@@ -108,16 +133,16 @@ __global__ __launch_bounds__(kWG) void k_rotate(RotArgs a, Small sm) {
 
 template <int KMAX>
 __global__ __launch_bounds__(kWG) void k_rotate_gram(RotArgs a, Small sm) {
-  // staging rows, then the per-wave pair sums: gram_lds_doubles(k - 1) doubles
+  // staging rows, then the per-wave pair sums: gram_lds_doubles(k - 1 + naug) doubles
   extern __shared__ double s_buf[];
   __shared__ double s_c[KMAX], s_s[KMAX];
-  const int kk = a.k - 1, np = kk * (kk - 1) / 2;
+  const int na = a.k - 1 + a.naug, np = na * (na - 1) / 2;
   givens_coefs(a, sm.cap, s_c, s_s, KMAX);
   __syncthreads();
   v4d acc[GramShape<KMAX>::NBP];
-  rotate_gram_body<KMAX>(a, s_c, s_s, blockIdx.x, gridDim.x, s_buf, gram_stride(kk), acc);
+  rotate_gram_body<KMAX>(a, s_c, s_s, blockIdx.x, gridDim.x, s_buf, gram_stride(na), acc);
   __syncthreads();  // the staging area becomes the per-wave pair accumulators
-  gram_store<KMAX>(acc, s_buf + (threadIdx.x >> 6) * np, kk);
+  gram_store<KMAX>(acc, s_buf + (threadIdx.x >> 6) * np, na);
   publish(sm, np, s_buf, np);
 }
 
@@ -238,16 +263,17 @@ hipError_t launch_rotate(const RotArgs& a, const Small& sm, const Tail& t, int g
   if (a.gram) {
     // dynamic LDS sized for the live columns: fewer columns, more resident
     // workgroups per compute unit
-    const size_t lds = sizeof(double) * (size_t)gram_lds_doubles(a.k - 1);
-    if (a.k <= 16)
+    const int na = a.k - 1 + a.naug;  // staged columns
+    const size_t lds = sizeof(double) * (size_t)gram_lds_doubles(na);
+    if (na <= 16)
       hipLaunchKernelGGL(k_rotate_gram<16>, dim3(grid), dim3(kWG), lds, st, a, sm);
-    else if (a.k <= 32)
+    else if (na <= 32)
       hipLaunchKernelGGL(k_rotate_gram<32>, dim3(grid), dim3(kWG), lds, st, a, sm);
-    else if (a.k <= 64)
+    else if (na <= 64)
       hipLaunchKernelGGL(k_rotate_gram<64>, dim3(grid), dim3(kWG), lds, st, a, sm);
     else
-      return hipErrorInvalidValue;  // the ICWY window is limited to 64 columns
-    return launch_finalize(sm, t, (a.k - 1) * (a.k - 2) / 2, grid, st);
+      return hipErrorInvalidValue;  // at most 64 staged columns
+    return launch_finalize(sm, t, na * (na - 1) / 2, grid, st);
   }
   hipLaunchKernelGGL(k_rotate, dim3(grid), dim3(kWG), 0, st, a, sm);
   return hipGetLastError();

@@ -489,7 +489,7 @@ __device__ __forceinline__ void rotate_row(const RotArgs& a, int64_t row, bool v
         const double cj = s_c[j], sj = s_s[j];
         const double qn = cj * x + sj * y;
         x = -sj * x + cj * y;
-        if (valid) qw[(int64_t)j * a.ldq] = qn;
+        if (valid) st1_stream(qn, qw + (int64_t)j * a.ldq);
         emit(j, valid ? qn : 0.0);
       }
     }
@@ -574,7 +574,9 @@ __host__ __device__ constexpr int gram_lds_doubles(int kk) {
 }
 
 // ICWY after QRDelete (Sec. 3.2): rotate, then accumulate the strict lower
-// Gram matrix of the kk = k-1 rotated columns, T_ab = q_a^T q_b (b < a).  The
+// Gram matrix of the kk = k-1 rotated columns, T_ab = q_a^T q_b (b < a)
+// (with a.naug > 0 the staged rows also carry v and f after the kk columns,
+// so the pairs (kk, b) and (kk + 1, b) are q_b^T v and q_b^T f).  The
 // Gram over rows is a dense contraction, done on the matrix cores: each wave
 // stages its 64 rotated rows in LDS (row stride kp = gram_stride(kk) doubles,
 // only the kk live columns) and, 4 rows at a time, issues v_mfma_f64_16x16x4
@@ -593,14 +595,17 @@ __device__ inline void rotate_gram_body(const RotArgs& a, const double* s_c, con
 #pragma unroll
   for (int p = 0; p < S::NBP; ++p) acc[p] = v4d{0.0, 0.0, 0.0, 0.0};
   const int64_t ntiles = (a.n + kWG - 1) / kWG;
-  const int kk = a.k - 1;
+  const int kk = a.k - 1, na = kk + a.naug;
   bool live[S::NB];
 #pragma unroll
-  for (int b = 0; b < S::NB; ++b) live[b] = b * 16 + li < kk;
+  for (int b = 0; b < S::NB; ++b) live[b] = b * 16 + li < na;
   for (int64_t tile = t0; tile < ntiles; tile += ts) {
     const int64_t row = tile * kWG + threadIdx.x;
+    const bool valid = row < a.n;
     double* srow = stage + lane * kp;
-    rotate_row(a, row, row < a.n, s_c, s_s, [&](int j, double v) { srow[j] = v; });
+    if (a.naug > 0) srow[kk] = valid ? ld1(a.v + row) : 0.0;
+    if (a.naug > 1) srow[kk + 1] = valid ? ld1(a.f + row) : 0.0;
+    rotate_row(a, row, valid, s_c, s_s, [&](int j, double v) { srow[j] = v; });
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

@@ -172,3 +172,28 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     with open(cache) as fh:
         lines = fh.read().split()
     assert len(lines) == 5 and lines[0].startswith("gfx")
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("flags", ["rhs", "rhs+delete", "delete"])
+def test_batch_fusion_options_match_oracle(variant, flags):
+    """The batched kernel with the right-hand side folded into QRAdd and/or
+    QRDelete sharing its pass with the QRAdd's first (ignored for MGS), 15
+    iterations against the oracle's separate steps."""
+    import torch
+    device()
+    from paper_2110_09667_amd import aa
+    f = {"rhs": aa.FUSE_RHS, "rhs+delete": aa.FUSE_RHS | aa.FUSE_DELETE,
+         "delete": aa.FUSE_DELETE}[flags]
+    insts, probs = small_table(count=8, seed0=123)
+    iters = 15
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = aa.AABatch(probs, [i.m for i in insts], variant, flags=f, tol=0.0, max_iter=10**9,
+                       stream=stream)
+        b.run(iters + 1)
+        states, _ = b.read()
+    for j, (inst, p) in enumerate(zip(insts, probs)):
+        xs, st, _ = O.run_aa(lambda u: O.G_stencil(p, u), np.zeros(p.n), inst.m, variant, iters)
+        assert rel(b.x[j].cpu().numpy(), xs[-1]) <= 1e-10, (j, inst)
+        assert states[j].status == 0 and states[j].k == min(inst.m, iters)

@@ -302,6 +302,84 @@ def test_aa_fused_rhs_matches_oracle(variant, m):
         assert rhs == (iters if variant == "mgs" else 1), rhs
 
 
+@pytest.mark.parametrize("variant", ["icwy", "cgs2", "dcgs2"])
+@pytest.mark.parametrize("m", [2, 3, 10, 17])
+@pytest.mark.parametrize("rhs", [False, True])
+def test_fused_delete_matches_oracle(variant, m, rhs):
+    """AA_FUSE_DELETE: QRDelete's rotation pass also contracts Delta f (and
+    f_i) against the rotated basis and replaces the QRAdd's first pass; 20
+    iterations against the oracle (window recycled from iteration m + 1).
+    Reductions per recycled iteration: the fused one plus the QRAdd's
+    remaining passes (ICWY 1, DCGS-2 1, CGS-2 2)."""
+    device()
+    aa = aa_mod()
+    flags = aa.FUSE_DELETE | (aa.FUSE_RHS if rhs else 0)
+    first = {"icwy": 2, "cgs2": 3, "dcgs2": 2}[variant]
+    for prob in (W.nonlinear3d(s=21, seed=6), W.poisson1d()):
+        iters = 20
+        xs_ref, _, _ = O.run_aa(lambda u: O.G_stencil(prob, u), np.zeros(prob.n), m, variant,
+                                iters)
+        xs, ctx = gpu_aa_run(prob, m, variant, iters, flags=flags, fused=False)
+        worst = max(rel(xs[i], xs_ref[i]) for i in range(1, iters + 2))
+        assert worst <= 1e-10, (prob.n, worst)
+        assert ctx.info().status == 0
+        add, dele, rhs_syncs = ctx.sync_counts()
+        recycled = iters - m  # iterations m+1 .. iters delete a column
+        fill_add = 1 + first * (m - 1)
+        assert dele == recycled, dele
+        assert add == fill_add + (first - 1) * recycled, (add, fill_add, recycled)
+        assert rhs_syncs == (1 if rhs else iters), rhs_syncs
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("m", [3, 10])
+def test_one_workgroup_step_with_fusion_matches_oracle_and_counts(variant, m):
+    """The one-workgroup step (small n) with AA_FUSE_RHS | AA_FUSE_DELETE:
+    iterates against the oracle, and the reduction and byte accounting equal
+    the grid-wide path's with the same flags."""
+    device()
+    aa = aa_mod()
+    flags = aa.FUSE_RHS | aa.FUSE_DELETE
+    prob = W.nonlinear3d(s=21, seed=6)
+    iters = 20
+    xs_ref, _, _ = O.run_aa(lambda u: O.G_stencil(prob, u), np.zeros(prob.n), m, variant, iters)
+    xs, c1 = gpu_aa_run(prob, m, variant, iters, flags=flags, fused=True)
+    worst = max(rel(xs[i], xs_ref[i]) for i in range(1, iters + 2))
+    assert worst <= 1e-10, worst
+    _, c2 = gpu_aa_run(prob, m, variant, iters, flags=flags, fused=False, record=False)
+    assert c1.sync_counts() == c2.sync_counts()
+
+
+@pytest.mark.parametrize("flags", [1 << 1, 1 << 4, (1 << 1) | (1 << 4)])
+def test_dcgs2_fused_delete_readings_match_oracle(flags):
+    """Both readings of Alg. 6 (A7, A8) with the fused delete and the folded
+    right-hand side."""
+    device()
+    aa = aa_mod()
+    prob = W.nonlinear3d(s=21, seed=6)
+    iters = 20
+    xs_ref, _, _ = O.run_aa(lambda u: O.G_stencil(prob, u), np.zeros(prob.n), 6, "dcgs2", iters,
+                            flags=flags)
+    xs, _ = gpu_aa_run(prob, 6, "dcgs2", iters, flags=flags | aa.FUSE_DELETE | aa.FUSE_RHS,
+                       fused=False)
+    worst = max(rel(xs[i], xs_ref[i]) for i in range(1, iters + 2))
+    assert worst <= 1e-10, worst
+
+
+@pytest.mark.parametrize("variant", ["icwy", "cgs2", "dcgs2"])
+def test_fused_delete_full_size_matches_separate(variant):
+    """256^3, m = 20: fused delete and folded right-hand side against the
+    separate passes on the GPU, 24 iterations."""
+    device()
+    aa = aa_mod()
+    prob = W.nonlinear3d()
+    a, _ = gpu_aa_run(prob, 20, variant, 24)
+    b, ctx = gpu_aa_run(prob, 20, variant, 24, flags=aa.FUSE_DELETE | aa.FUSE_RHS)
+    assert ctx.info().status == 0
+    worst = max(rel(b[i], a[i]) for i in range(1, 26))
+    assert worst <= 1e-10, worst
+
+
 @pytest.mark.parametrize("flags", [1 << 1, 1 << 4, (1 << 1) | (1 << 4)])
 def test_dcgs2_fused_rhs_readings_match_oracle(flags):
     """DCGS-2's fused Q^T f corrects c_{k-1} for the reorthogonalized previous
