@@ -173,24 +173,36 @@ class BatchProblem2D:
         aa.aa_fill_uniform(self.f, inst.seed, 1)
 
 
-def batch_iter_vectors(variant, m, m_i, k_before):
-    """Algorithmic n-vectors of one batched iteration of one instance (the
-    same byte model as the single-instance path, G included)."""
+def batch_iter_vectors(variant, m, m_i, k_before, fuse=0):
+    """Algorithmic n-vectors of one batched iteration of one instance with a
+    full window (the same byte model as the library's accounting, G
+    included)."""
+    from paper_2110_09667_amd import aa
     k = k_before
     add = {"mgs": 4 * k + 3 if k else 3, "cgs2": 3 * k + 6, "dcgs2": 2 * k + (6 if k >= 3 else 5),
            "icwy": 2 * k + 5}[variant]
     delete = (2 * m - 1) if m_i == m else 0
-    return 3 + 8 + delete + add + (m_i + 1) + (m_i + 3)
+    rhs = m_i + 1
+    fold = bool(fuse & aa.FUSE_RHS) and variant != "mgs" and k >= 1
+    fused_del = bool(fuse & aa.FUSE_DELETE) and variant != "mgs" and m_i == m and k >= 1
+    if fused_del:
+        add -= k + 1
+        delete += 2 if fold else 1
+    if fold:
+        rhs = 0
+        add += 1 if fused_del else 2
+    return 3 + 8 + delete + add + rhs + (m_i + 3)
 
 
-def batched_run(probs, ms, variant, tol, cap, chunk, stream, net=None, steady=20, tune=True):
+def batched_run(probs, ms, variant, tol, cap, chunk, stream, net=None, steady=20, tune=True,
+                fuse=0):
     """Drive a batch to tolerance (or the iteration cap): returns the time of
     the first 21 iterations (every window full after them), the schedule the
     autotuner picked (plain batches), the steady per-iteration time, the wall
     time until no instance is active and the final states."""
     import torch
     from paper_2110_09667_amd import aa
-    flags = aa.BATCH_LEARNED if net is not None else 0
+    flags = (aa.BATCH_LEARNED if net is not None else 0) | fuse
     b = aa.AABatch(probs, ms, variant, flags=flags, tol=tol, max_iter=cap, stream=stream)
 
     def run(k):
@@ -288,7 +300,7 @@ def poisson1d_to_tolerance(variant, tol=1e-8, cap=300, check_every=1):
             "oracle_iterations": len(res), "oracle_ms": round(1e3 * cpu_s, 3)}
 
 
-def one_at_a_time(probs, ms, variant, tol, cap, check_every=10):
+def one_at_a_time(probs, ms, variant, tol, cap, check_every=10, flags=0):
     """The same instances solved one after another through the single-instance
     entry points (aa_problem_apply + aa_step on one context per instance),
     each until ||f_i|| <= tol ||f_0|| (tested every ``check_every`` steps) or
@@ -297,7 +309,7 @@ def one_at_a_time(probs, ms, variant, tol, cap, check_every=10):
     from paper_2110_09667_amd import aa
     out = []
     for p, m in zip(probs, ms):
-        ctx = aa.AAContext(p.n, m, variant)
+        ctx = aa.AAContext(p.n, m, variant, flags)
         x = torch.zeros(p.n, dtype=torch.float64, device="cuda:0")
         g = torch.empty_like(x)
         torch.cuda.synchronize()
@@ -319,7 +331,7 @@ def one_at_a_time(probs, ms, variant, tol, cap, check_every=10):
     return out
 
 
-def batched_suite(variant, count, cap, train_count, train_iters, sample, lr=1e-3):
+def batched_suite(variant, count, cap, train_count, train_iters, sample, lr=1e-3, fuse=0):
     """Batched AA on the 2D workload table (instance seeds 0..count-1):
     plain batched to tol 1e-8 (or the cap), the learned-guarded batch with a
     network trained on instances of disjoint seeds, and a seeded sample of
@@ -336,11 +348,15 @@ def batched_suite(variant, count, cap, train_count, train_iters, sample, lr=1e-3
     sum_n = sum(p.n for p in probs)
     stream = torch.cuda.Stream()
     res = {"instances": count, "sum_n": sum_n, "variant": variant, "tol": tol,
-           "max_iter": cap}
+           "max_iter": cap,
+           "passes": ("RHS folded into QRAdd, QRDelete fused with its first pass"
+                      if fuse == (aa.FUSE_RHS | aa.FUSE_DELETE) else
+                      "separate" if fuse == 0 else f"flags {fuse}")}
     with torch.cuda.stream(stream):
         # algorithmic bytes of one full-window iteration of every instance
-        vec = sum(batch_iter_vectors(variant, i.m, i.m, i.m - 1) * p.n for i, p in zip(insts, probs))
-        plain = batched_run(probs, ms, variant, tol, cap, 50, stream)
+        vec = sum(batch_iter_vectors(variant, i.m, i.m, i.m - 1, fuse) * p.n
+                  for i, p in zip(insts, probs))
+        plain = batched_run(probs, ms, variant, tol, cap, 50, stream, fuse=fuse)
         print(f"# batched plain: {plain['steady_ms_per_iter']:.2f} ms/iter, "
               f"{plain['wall_s']:.1f} s", file=sys.stderr, flush=True)
         # training on disjoint seeds: plain-AA trajectories, one Adam step per
@@ -348,7 +364,7 @@ def batched_suite(variant, count, cap, train_count, train_iters, sample, lr=1e-3
         tinsts = W.batch_table(train_count, first_seed=W.SEED_TRAIN_BASE)
         tprobs = [BatchProblem2D(i) for i in tinsts]
         net = aa.AAMlp(max(count, train_count), seed=1, stream=stream)
-        tb = aa.AABatch(tprobs, [i.m for i in tinsts], variant, flags=aa.BATCH_LEARNED,
+        tb = aa.AABatch(tprobs, [i.m for i in tinsts], variant, flags=aa.BATCH_LEARNED | fuse,
                         tol=0.0, max_iter=10**9, stream=stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -359,18 +375,19 @@ def batched_suite(variant, count, cap, train_count, train_iters, sample, lr=1e-3
         tb.close()
         del tb, tprobs
         torch.cuda.empty_cache()
-        learned = batched_run(probs, ms, variant, tol, cap, 50, stream, net=net)
+        learned = batched_run(probs, ms, variant, tol, cap, 50, stream, net=net, fuse=fuse)
         print(f"# batched learned: {learned['steady_ms_per_iter']:.2f} ms/iter, "
               f"{learned['wall_s']:.1f} s", file=sys.stderr, flush=True)
         # ablation: the same guard with the untrained network (delta gamma = 0,
         # beta = sigmoid(4)): what the training itself adds
         net0 = aa.AAMlp(count, seed=1, stream=stream)
-        untrained = batched_run(probs, ms, variant, tol, cap, 50, stream, net=net0)
+        untrained = batched_run(probs, ms, variant, tol, cap, 50, stream, net=net0, fuse=fuse)
         print(f"# batched guarded, untrained network: {untrained['wall_s']:.1f} s",
               file=sys.stderr, flush=True)
     rng = np.random.default_rng(12345)
     pick = sorted(rng.choice(count, size=min(sample, count), replace=False).tolist())
-    single = one_at_a_time([probs[j] for j in pick], [ms[j] for j in pick], variant, tol, cap)
+    single = one_at_a_time([probs[j] for j in pick], [ms[j] for j in pick], variant, tol, cap,
+                           flags=fuse)
     print(f"# one at a time ({len(pick)} sampled): {sum(t for t, _, _ in single):.1f} s",
           file=sys.stderr, flush=True)
 
@@ -505,6 +522,9 @@ def main():
     ap.add_argument("--rhs", choices=["separate", "fused"], default="separate",
                     help="R gamma = Q^T f_i as its own pass (as Alg. 2 writes it) or folded "
                          "into the QRAdd passes (AA_FUSE_RHS)")
+    ap.add_argument("--batch-passes", choices=["separate", "fused"], default="fused",
+                    help="batched runs with the paper's separate passes or with the RHS folded "
+                         "into QRAdd and QRDelete fused with its first pass")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched / learned-guarded / one-at-a-time comparison")
     ap.add_argument("--batch-count", type=int, default=4096)
@@ -625,7 +645,9 @@ def main():
     batched = None
     if not args.no_batch:
         batched = batched_suite(args.variant, args.batch_count, args.batch_cap, args.train_count,
-                                args.train_iters, args.single_sample)
+                                args.train_iters, args.single_sample,
+                                fuse=(aa.FUSE_RHS | aa.FUSE_DELETE)
+                                if args.batch_passes == "fused" else 0)
 
     kern = main_res["kernels"]
     dom = max((k for k in kern if kern[k]["bytes"] > 0), key=lambda k: kern[k]["ms"])
