@@ -277,15 +277,17 @@ def poisson1d_to_tolerance(variant, tol=1e-8, cap=300, check_every=1):
     # the same solve through the batched entry points with one instance: the
     # stop test runs on the device, one launch per iteration, one wait at the end
     stream = torch.cuda.Stream()
+    batch_s = {}
     with torch.cuda.stream(stream):
-        b = aa.AABatch([prob], [m], variant, tol=tol, max_iter=cap, stream=stream)
-        b.set_schedule(use_graph=False)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        b.run(cap + 1)
-        bst, _ = b.read()
-        batch_s = time.perf_counter() - t0
-        b.close()
+        for label, flags in (("separate", 0), ("fused", aa.FUSE_RHS | aa.FUSE_DELETE)):
+            b = aa.AABatch([prob], [m], variant, flags=flags, tol=tol, max_iter=cap, stream=stream)
+            b.set_schedule(use_graph=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.run(cap + 1)
+            bst, _ = b.read()
+            batch_s[label] = time.perf_counter() - t0
+            b.close()
     if not os.path.exists(O.LIB_PATH):
         O.build()
     t0 = time.perf_counter()
@@ -296,7 +298,8 @@ def poisson1d_to_tolerance(variant, tol=1e-8, cap=300, check_every=1):
             "final_rel_residual": info.res_norm / info.res0_norm,
             "gpu_ms": round(1e3 * gpu_s, 3), "us_per_iter": round(1e6 * gpu_s / max(it, 1), 1),
             "batch_api_iterations": int(bst[0].stop_iter if not bst[0].active else bst[0].iter),
-            "batch_api_ms": round(1e3 * batch_s, 3),
+            "batch_api_ms": round(1e3 * batch_s["separate"], 3),
+            "batch_api_fused_passes_ms": round(1e3 * batch_s["fused"], 3),
             "oracle_iterations": len(res), "oracle_ms": round(1e3 * cpu_s, 3)}
 
 

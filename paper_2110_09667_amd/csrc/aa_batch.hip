@@ -600,8 +600,12 @@ __device__ BState wg_instance(const BatchArgs& b, const BInst& I, BState st, L& 
   }
 }
 
+// At least two waves per SIMD (eight per compute unit): without the bound the
+// compiler spends up to 256 registers per lane on this large kernel and only
+// one workgroup fits a compute unit; with it (no extra spills) the batched
+// iteration of the 4096-instance workload runs 1.5x faster.
 template <int KB, bool GRAM>
-__global__ __launch_bounds__(kWG) void k_batch(BatchArgs b) {
+__global__ __launch_bounds__(kWG, 2) void k_batch(BatchArgs b) {
   using L = BatchLds<KB, GRAM>;
   __shared__ L lds;
   __shared__ int s_idx;
