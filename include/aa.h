@@ -73,13 +73,16 @@ enum {
    * reduction per iteration.  MGS and the first QRAdd keep the separate
    * pass. */
   AA_FUSE_RHS = 1u << 3,
-  /* aa_step with ICWY once the window is full: QRDelete's rotation pass also
-   * stages Delta f (and f_i with AA_FUSE_RHS) beside the rotated columns, so
-   * the one matrix-core contraction that refreshes T (Sec. 3.2) also yields
-   * Q^T Delta f, the first reduction of the QRAdd that follows (Alg. 4).
-   * Same quantities, different rounding order; one pass over Q and one
-   * reduction fewer per iteration (ICWY: 2 instead of 3 with the delete).
-   * Windows up to 62 columns (63 without AA_FUSE_RHS). */
+  /* aa_step (and the batched entry points) with CGS-2, DCGS-2 or ICWY once
+   * the window is full: QRDelete's rotation pass also stages Delta f (and
+   * f_i with AA_FUSE_RHS) beside the rotated columns, and one matrix-core
+   * Gram of [Q Delta f f] yields ICWY's T refresh (Sec. 3.2) together with
+   * every block dot product of the QRAdd's first pass (Algs. 4-6: Q^T Delta
+   * f, the Gram row of the last column, Q^T f_i).  Same quantities, different
+   * rounding order; one pass over Q fewer per iteration, and for ICWY one
+   * reduction fewer (2 per iteration including the delete instead of 3).
+   * MGS is unaffected.  Windows of up to 62 columns (63 without
+   * AA_FUSE_RHS); wider ones keep the separate passes. */
   AA_FUSE_DELETE = 1u << 5,
   /* Workspace for the QR update only (aa_qr_add / aa_qr_delete /
    * aa_qr_solve); aa_step is then unavailable.  Saves (m + 3) n doubles. */
@@ -249,7 +252,11 @@ aa_status aa_batch_workspace_size(int count, const aa_batch_instance *h_inst,
 
 /* h_inst: count descriptors (host; copied).  The workspace (device,
  * 256-byte aligned, caller-owned) holds every instance's Q, history, R, T and
- * the schedule.  stream: a hipStream_t; a non-NULL stream lets aa_batch_run
+ * the schedule.  flags: the QRAdd readings of aa_init (AA_DCGS2_LITERAL,
+ * AA_DCGS2_GUARD_GE3), the pass fusions AA_FUSE_RHS and AA_FUSE_DELETE, and
+ * AA_BATCH_LEARNED.  Each instance stops (on the device) at the start of the
+ * first iteration with ||f_i|| <= tol ||f_0||, at max_iter, or on a
+ * breakdown.  stream: a hipStream_t; a non-NULL stream lets aa_batch_run
  * replay a captured HIP graph. */
 aa_status aa_batch_init(aa_batch **b, int count, const aa_batch_instance *h_inst,
                         int variant, unsigned flags, double tol, int64_t max_iter,
