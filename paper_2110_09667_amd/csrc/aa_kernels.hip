@@ -131,19 +131,30 @@ __global__ __launch_bounds__(kWG) void k_rotate(RotArgs a, Small sm) {
   rotate_body(a, s_c, s_s, blockIdx.x, gridDim.x);
 }
 
-template <int KMAX>
-__global__ __launch_bounds__(kWG) void k_rotate_gram(RotArgs a, Small sm) {
-  // staging rows, then the per-wave pair sums: gram_lds_doubles(k - 1 + naug) doubles
+// WAVES waves per workgroup: wide Gram staging (KMAX = 64 needs 25 KiB per
+// wave) uses two-wave workgroups so that three of them share a compute unit
+// (six waves) instead of one four-wave workgroup.
+template <int KMAX, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_rotate_gram(RotArgs a, Small sm) {
+  // staging rows, then the per-wave pair sums: gram_lds_doubles(k - 1 + naug, WAVES)
   extern __shared__ double s_buf[];
   __shared__ double s_c[KMAX], s_s[KMAX];
   const int na = a.k - 1 + a.naug, np = na * (na - 1) / 2;
   givens_coefs(a, sm.cap, s_c, s_s, KMAX);
   __syncthreads();
   v4d acc[GramShape<KMAX>::NBP];
-  rotate_gram_body<KMAX>(a, s_c, s_s, blockIdx.x, gridDim.x, s_buf, gram_stride(na), acc);
+  rotate_gram_body<KMAX, 64 * WAVES>(a, s_c, s_s, blockIdx.x, gridDim.x, s_buf,
+                                     gram_stride(na), acc);
   __syncthreads();  // the staging area becomes the per-wave pair accumulators
   gram_store<KMAX>(acc, s_buf + (threadIdx.x >> 6) * np, na);
-  publish(sm, np, s_buf, np);
+  __syncthreads();
+  const int G = gridDim.x, b = blockIdx.x;
+  for (int c = threadIdx.x; c < np; c += 64 * WAVES) {
+    double s = s_buf[c];
+#pragma unroll
+    for (int w = 1; w < WAVES; ++w) s += s_buf[w * np + c];
+    sm.partials[(size_t)c * G + b] = s;
+  }
 }
 
 __global__ __launch_bounds__(kWG) void k_scale(ScaleArgs a) {
@@ -264,15 +275,18 @@ hipError_t launch_rotate(const RotArgs& a, const Small& sm, const Tail& t, int g
     // dynamic LDS sized for the live columns: fewer columns, more resident
     // workgroups per compute unit
     const int na = a.k - 1 + a.naug;  // staged columns
-    const size_t lds = sizeof(double) * (size_t)gram_lds_doubles(na);
-    if (na <= 16)
-      hipLaunchKernelGGL(k_rotate_gram<16>, dim3(grid), dim3(kWG), lds, st, a, sm);
-    else if (na <= 32)
-      hipLaunchKernelGGL(k_rotate_gram<32>, dim3(grid), dim3(kWG), lds, st, a, sm);
-    else if (na <= 64)
-      hipLaunchKernelGGL(k_rotate_gram<64>, dim3(grid), dim3(kWG), lds, st, a, sm);
-    else
+    if (na <= 16) {
+      const size_t lds = sizeof(double) * (size_t)gram_lds_doubles(na, kWaves);
+      hipLaunchKernelGGL((k_rotate_gram<16, kWaves>), dim3(grid), dim3(kWG), lds, st, a, sm);
+    } else if (na <= 32) {
+      const size_t lds = sizeof(double) * (size_t)gram_lds_doubles(na, kWaves);
+      hipLaunchKernelGGL((k_rotate_gram<32, kWaves>), dim3(grid), dim3(kWG), lds, st, a, sm);
+    } else if (na <= 64) {
+      const size_t lds = sizeof(double) * (size_t)gram_lds_doubles(na, 2);
+      hipLaunchKernelGGL((k_rotate_gram<64, 2>), dim3(grid), dim3(128), lds, st, a, sm);
+    } else {
       return hipErrorInvalidValue;  // at most 64 staged columns
+    }
     return launch_finalize(sm, t, na * (na - 1) / 2, grid, st);
   }
   hipLaunchKernelGGL(k_rotate, dim3(grid), dim3(kWG), 0, st, a, sm);

@@ -129,11 +129,33 @@ __global__ void k_gelu_back(const float* dh, const float* z, float* dz, uint16_t
 }
 
 // db[j] += sum_r dz[r][j] (fixed order over r; one thread per column)
-__global__ void k_colsum_acc(const float* dz, int rows, int cols, float* db) {
+// Bias gradient db[j] += sum_r dz[r][j] in two fixed-order stages: block
+// (x, y) sums columns 64x..64x+63 over the y-th of kColSplit row slices (four
+// row phases per thread, combined in LDS) into part[y][j]; k_colsum_fin adds
+// the kColSplit partial sums in order.
+constexpr int kColSplit = 32;
+
+__global__ __launch_bounds__(256) void k_colsum_part(const float* dz, int rows, int cols,
+                                                     float* part) {
+  __shared__ float red[4][64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + tx;
+  const int per = (rows + kColSplit - 1) / kColSplit;
+  const int r0 = blockIdx.y * per, r1 = r0 + per < rows ? r0 + per : rows;
+  float s = 0.f;
+  if (j < cols)
+    for (int r = r0 + ty; r < r1; r += 4) s += dz[(int64_t)r * cols + j];
+  red[ty][tx] = s;
+  __syncthreads();
+  if (ty == 0 && j < cols)
+    part[(size_t)blockIdx.y * cols + j] = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
+}
+
+__global__ void k_colsum_fin(const float* part, int cols, float* db) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= cols) return;
   float s = 0.f;
-  for (int r = 0; r < rows; ++r) s += dz[(int64_t)r * cols + j];
+  for (int y = 0; y < kColSplit; ++y) s += part[(size_t)y * cols + j];
   db[j] += s;
 }
 
@@ -248,6 +270,7 @@ struct aa_mlp {
   uint16_t* h[kLayers] = {};                                       // h[l] = input of layer l (l >= 1)
   float *dz = nullptr, *dh = nullptr;
   uint16_t* dzb = nullptr;
+  float* colpart = nullptr;  // kColSplit x 256 bias-gradient partial sums
   int last_batch = 0;
   int64_t t = 0;  // Adam steps taken
   int64_t off_w[kLayers], off_b[kLayers];
@@ -282,6 +305,7 @@ aa_status aa_mlp_workspace_size(int max_batch, size_t* bytes) {
   s += 3 * al(sizeof(float) * B * kH) + al(sizeof(float) * B * kOutP);
   s += 3 * al(sizeof(uint16_t) * B * kH);
   s += 2 * al(sizeof(float) * B * kH) + al(sizeof(uint16_t) * B * kH);
+  s += al(sizeof(float) * kColSplit * kH);
   *bytes = s;
   return AA_OK;
 }
@@ -318,6 +342,7 @@ aa_status aa_mlp_init(aa_mlp** out, int max_batch, uint64_t seed, void* d_ws, si
   n->dz = (float*)take(sizeof(float) * B * kH);
   n->dh = (float*)take(sizeof(float) * B * kH);
   n->dzb = (uint16_t*)take(sizeof(uint16_t) * B * kH);
+  n->colpart = (float*)take(sizeof(float) * kColSplit * kH);
   int64_t off = 0;
   for (int l = 0; l < kLayers; ++l) {
     n->off_w[l] = off;
@@ -436,7 +461,9 @@ aa_status aa_mlp_backward(aa_mlp* n, int batch, const float* dout) {
     gw.K = batch;
     gw.accumulate = 1;
     if (gemm(gw, st) != hipSuccess) return AA_EHIP;
-    hipLaunchKernelGGL(k_colsum_acc, dim3((dout_l + 255) / 256), dim3(256), 0, st, n->dz, batch,
+    hipLaunchKernelGGL(k_colsum_part, dim3((dout_l + 63) / 64, kColSplit), dim3(256), 0, st,
+                       n->dz, batch, dout_l, n->colpart);
+    hipLaunchKernelGGL(k_colsum_fin, dim3((dout_l + 255) / 256), dim3(256), 0, st, n->colpart,
                        dout_l, n->g + n->off_b[l]);
     if (l == 0) break;
     // dH = dZ_l W_l^T   (M = batch, N = din, K = dout)

@@ -565,12 +565,12 @@ struct GramShape {
 // that the 64 lanes of a wave writing one row each spread over all banks.
 __host__ __device__ constexpr int gram_stride(int kk) { return kk | 1; }
 
-// Staging doubles a workgroup needs for kk rotated columns (the same area
-// later holds the per-wave pair sums).
-__host__ __device__ constexpr int gram_lds_doubles(int kk) {
-  return kWaves * 64 * gram_stride(kk) > kWaves * (kk * (kk - 1) / 2)
-             ? kWaves * 64 * gram_stride(kk)
-             : kWaves * (kk * (kk - 1) / 2);
+// Staging doubles a workgroup of `waves` waves needs for kk staged columns
+// (the same area later holds the per-wave pair sums).
+__host__ __device__ constexpr int gram_lds_doubles(int kk, int waves = kWaves) {
+  return waves * 64 * gram_stride(kk) > waves * (kk * (kk - 1) / 2)
+             ? waves * 64 * gram_stride(kk)
+             : waves * (kk * (kk - 1) / 2);
 }
 
 // ICWY after QRDelete (Sec. 3.2): rotate, then accumulate the strict lower
@@ -584,7 +584,7 @@ __host__ __device__ constexpr int gram_lds_doubles(int kk) {
 // kk.  Operand layout of that instruction: lane l supplies A[l % 16][l / 16]
 // and B[l / 16][l % 16]; lane l, register r of the result holds
 // D[l / 16 + 4 r][l % 16].  Accumulators stay in registers across all tiles.
-template <int KMAX>
+template <int KMAX, int WG = kWG>
 __device__ inline void rotate_gram_body(const RotArgs& a, const double* s_c, const double* s_s,
                                         int64_t t0, int64_t ts, double* stage_all, int kp,
                                         v4d (&acc)[GramShape<KMAX>::NBP]) {
@@ -594,13 +594,13 @@ __device__ inline void rotate_gram_body(const RotArgs& a, const double* s_c, con
   double* stage = stage_all + w * 64 * kp;
 #pragma unroll
   for (int p = 0; p < S::NBP; ++p) acc[p] = v4d{0.0, 0.0, 0.0, 0.0};
-  const int64_t ntiles = (a.n + kWG - 1) / kWG;
+  const int64_t ntiles = (a.n + WG - 1) / WG;
   const int kk = a.k - 1, na = kk + a.naug;
   bool live[S::NB];
 #pragma unroll
   for (int b = 0; b < S::NB; ++b) live[b] = b * 16 + li < na;
   for (int64_t tile = t0; tile < ntiles; tile += ts) {
-    const int64_t row = tile * kWG + threadIdx.x;
+    const int64_t row = tile * WG + threadIdx.x;
     const bool valid = row < a.n;
     double* srow = stage + lane * kp;
     if (a.naug > 0) srow[kk] = valid ? ld1(a.v + row) : 0.0;
