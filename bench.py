@@ -102,6 +102,49 @@ def run_variant(prob, m, variant, steps, warmup, grid=None, profile=True, flags=
     return out
 
 
+def graph_replay(sizes=(32, 48, 64, 96, 128), m=20, variant="icwy", steps=40):
+    """Mid-size 3D workloads, where an iteration is launch-bound: ms per AA
+    step (G included) enqueuing every pass vs. replaying captured graphs of
+    the steady-state iteration (aa_set_graph)."""
+    import torch
+    from paper_2110_09667_amd import aa
+    out = {}
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for s_ in sizes:
+            prob = Problem3D(s_)
+            f_d = device_rhs(prob)
+            row = {}
+            for graph in (False, True):
+                ctx = aa.AAContext(prob.n, m, variant, stream=stream)
+                ctx.set_fused_threshold(0)
+                ctx.set_graph(graph)
+                x = torch.zeros(prob.n, dtype=torch.float64, device="cuda:0")
+                g = torch.empty_like(x)
+
+                def step():
+                    aa.aa_problem_apply(3, s_, prob.h, prob.omega, prob.c, f_d, x, g,
+                                        stream=stream)
+                    ctx.step(x, g, x)
+
+                for _ in range(2 * m + 2):  # fill the window; capture every phase
+                    step()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    step()
+                torch.cuda.synchronize()
+                row["graph_ms" if graph else "direct_ms"] = round(
+                    1e3 * (time.perf_counter() - t0) / steps, 4)
+                ctx.close()
+            row["n"] = prob.n
+            row["speedup"] = round(row["direct_ms"] / row["graph_ms"], 3)
+            out[f"s={s_}"] = row
+            print(f"# graph replay s={s_} (n={prob.n}): direct {row['direct_ms']:.3f} ms, "
+                  f"graph {row['graph_ms']:.3f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def qr_micro(n, ks, variant, reps=3):
     """QRAdd / QRDelete on their own (the standalone microbenchmark): a basis
     of k orthonormal columns (seeded Gaussian columns added one by one), then
@@ -633,6 +676,8 @@ def main():
                                                   for k, d in m_sweep[v].items()),
                   file=sys.stderr, flush=True)
 
+    graphs = graph_replay() if not args.no_other_variants else {}
+
     qradd = {}
     if not args.no_qr_micro:
         # QRAdd / QRDelete alone: at the 3D workload's n with k = m - 1 (the
@@ -707,6 +752,7 @@ def main():
         "cpu_baseline": cpu,
         "poisson1d_to_1e-8": poisson,
         "m_sweep": m_sweep,
+        "graph_replay_icwy_m20": graphs,
         "fused_rhs": fused_rhs,
         "qradd": qradd,
         "batched": batched,

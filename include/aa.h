@@ -125,6 +125,18 @@ aa_status aa_set_stream(aa_ctx *ctx, void *stream);
 aa_status aa_step(aa_ctx *ctx, const double *d_x, const double *d_g,
                   double *d_x_next);
 
+/* Replay steady-state iterations from HIP graphs (enable 1) or enqueue every
+ * pass (0, the default).  Alg. 1 repeats the same passes once the window is
+ * full; with graphs on, aa_step captures that iteration the first time each
+ * ring-slot phase (i - 1) mod m comes round with the given x, G(x), x_next
+ * pointers and replays it afterwards (one launch instead of about a dozen,
+ * which at n below a few million is what an iteration costs).  Needs a
+ * non-NULL stream; not used while profiling, for the one-workgroup step, or
+ * after aa_qr_add / aa_qr_delete left k != m.  New pointers recapture that
+ * phase; aa_reset, aa_set_stream, aa_set_grid, aa_set_fused_threshold and
+ * aa_qr_load drop the graphs. */
+aa_status aa_set_graph(aa_ctx *ctx, int enable);
+
 /* Waits for the context's stream and reports the state of the last step. */
 aa_status aa_get_info(aa_ctx *ctx, aa_info *h_info);
 
@@ -204,7 +216,8 @@ aa_status aa_profile_reset(aa_ctx *ctx);
 aa_status aa_set_grid(aa_ctx *ctx, int stream_max, int gram_max);
 
 /* Largest n for which aa_step runs the whole iteration in one workgroup (one
- * launch instead of one per pass; default 16384, 0 disables, m <= 64). */
+ * launch instead of one per pass; default 20480 / m -- beyond that the
+ * grid-wide passes are faster; 0 disables; m <= 64). */
 aa_status aa_set_fused_threshold(aa_ctx *ctx, int64_t n_max);
 
 /* ---------------- batched AA: many independent instances ------------------ */

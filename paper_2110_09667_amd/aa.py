@@ -30,7 +30,7 @@ SYMBOLS = [
     "aa_qr_add", "aa_qr_delete", "aa_qr_solve", "aa_get_qr", "aa_qr_basis",
     "aa_qr_load", "aa_reset", "aa_destroy", "aa_sync_counts", "aa_problem_apply",
     "aa_fill_uniform", "aa_fill_normal", "aa_version", "aa_profile_enable",
-    "aa_profile_read", "aa_profile_reset", "aa_set_grid", "aa_set_fused_threshold",
+    "aa_profile_read", "aa_profile_reset", "aa_set_grid", "aa_set_fused_threshold", "aa_set_graph",
     "aa_batch_workspace_size", "aa_batch_init", "aa_batch_run", "aa_batch_read",
     "aa_batch_set_schedule", "aa_batch_autotune", "aa_batch_destroy", "aa_mlp_param_count",
     "aa_mlp_workspace_size", "aa_mlp_init", "aa_mlp_reseed", "aa_mlp_set_params",
@@ -112,6 +112,7 @@ def lib():
         "aa_profile_reset": [P],
         "aa_set_grid": [P, I, I],
         "aa_set_fused_threshold": [P, I64],
+        "aa_set_graph": [P, I],
         "aa_batch_workspace_size": [I, C.POINTER(BatchInstance), I, U, C.POINTER(C.c_size_t)],
         "aa_batch_init": [C.POINTER(P), I, C.POINTER(BatchInstance), I, U, D, I64, P,
                           C.c_size_t, P],
@@ -372,6 +373,10 @@ class AAContext:
 
     def set_grid(self, stream_max: int, gram_max: int):
         aa_set_grid(self.ctx, stream_max, gram_max)
+
+    def set_graph(self, enable: bool = True):
+        """Replay steady-state iterations from HIP graphs (see aa_set_graph)."""
+        _check(lib().aa_set_graph(self.ctx, 1 if enable else 0), "aa_set_graph")
 
     def set_fused_threshold(self, n_max: int):
         aa_set_fused_threshold(self.ctx, n_max)

@@ -34,7 +34,18 @@ struct aa_ctx {
   // fused single-workgroup step for small n (aa_batch.hip)
   BInst* d_binst = nullptr;
   BState* d_bstate = nullptr;
-  int64_t fused_max = 16384;
+  int64_t fused_max = 0;  // set by aa_init: kFusedWork / m
+  // steady-state iterations replayed as HIP graphs (aa_set_graph): one per
+  // ring-slot phase (i - 1) mod m, valid for the caller pointers it captured
+  struct StepGraph {
+    hipGraphExec_t exec = nullptr;
+    const double* x = nullptr;
+    const double* g = nullptr;
+    double* xn = nullptr;
+    int64_t d_add = 0, d_del = 0, d_rhs = 0;
+  };
+  bool graph_on = false;
+  std::vector<StepGraph> graphs;
   // per-launch timing (aa_profile_enable)
   bool prof_on = false;
   std::vector<hipEvent_t> ev;   // per launch p: 3p start, 3p+1 pass end, 3p+2 stop
@@ -114,6 +125,14 @@ int grid_stream(const aa_ctx* c) { return grid_for(c, kTile, c->grid_stream_max)
 int grid_rows(const aa_ctx* c, int gmax) { return grid_for(c, kWG, gmax); }
 
 constexpr int kEventPairs = 4096;
+
+// Default reach of the one-workgroup step: n * m <= kFusedWork.  One
+// workgroup streams ~23 GB/s, so its iteration costs ~2 ns per n*m element on
+// top of ~45 us; the grid-wide passes cost ~90 us at small n (about a dozen
+// dependent launches).  They break even near n * m = 20480 (measured on the
+// 3D workload: n = 13824, m = 20 took 0.65 ms in one workgroup; n = 32768
+// took 0.09 ms on the grid path).
+constexpr int64_t kFusedWork = 20480;
 
 hipError_t prof_drain(aa_ctx* c) {
   if (c->ev_used == 0) return hipSuccess;
@@ -498,6 +517,12 @@ aa_status fused_step(aa_ctx* c, const double* x, const double* g, double* x_next
   return AA_OK;
 }
 
+void drop_graphs(aa_ctx* c) {
+  for (auto& sg : c->graphs)
+    if (sg.exec) (void)hipGraphExecDestroy(sg.exec);
+  c->graphs.clear();
+}
+
 }  // namespace
 
 extern "C" {
@@ -525,6 +550,7 @@ aa_status aa_init(aa_ctx** ctx, int64_t n, int m, int variant, unsigned flags,
   c->n = n;
   c->ldq = L.ldq;
   c->m = m;
+  c->fused_max = kFusedWork / m;
   c->cap = m;
   c->variant = variant;
   c->flags = flags;
@@ -574,14 +600,16 @@ aa_status aa_init(aa_ctx** ctx, int64_t n, int m, int variant, unsigned flags,
 }
 
 aa_status aa_set_stream(aa_ctx* c, void* stream) {
+  if (c) drop_graphs(c);
   if (!c) return AA_EINVAL;
   c->stream = (hipStream_t)stream;
   return AA_OK;
 }
 
-aa_status aa_step(aa_ctx* c, const double* x, const double* g, double* x_next) {
-  if (!c || !x || !g || !x_next || (c->flags & AA_QR_ONLY)) return AA_EINVAL;
-  if (x_next == g) return AA_EINVAL;
+
+// One iteration of Alg. 1 enqueued kernel by kernel (host sequencing).
+static aa_status step_enqueue(aa_ctx* c, const double* x, const double* g,
+                              double* x_next) {
   if (c->d_binst && c->n <= c->fused_max) return fused_step(c, x, g, x_next);
   const hipStream_t st = c->stream;
   const int G = grid_stream(c);
@@ -624,6 +652,72 @@ aa_status aa_step(aa_ctx* c, const double* x, const double* g, double* x_next) {
     return AA_EHIP;
   c->m_i = m_i;
   c->iter = i + 1;
+  return AA_OK;
+}
+
+// With graphs on, a steady-state iteration (window full, grid-wide passes) is
+// replayed from a HIP graph captured the first time its ring-slot phase comes
+// round with these caller pointers; the host then only advances its counters
+// by what the captured iteration did.
+static aa_status step_graph(aa_ctx* c, const double* x, const double* g, double* x_next) {
+  const int phase = (int)((c->iter - 1) % c->m);
+  if ((int)c->graphs.size() != c->m) {
+    drop_graphs(c);
+    c->graphs.resize(c->m);
+  }
+  aa_ctx::StepGraph& sg = c->graphs[phase];
+  if (sg.exec && sg.x == x && sg.g == g && sg.xn == x_next) {
+    if (hipGraphLaunch(sg.exec, c->stream) != hipSuccess) return AA_EHIP;
+    c->syncs_add += sg.d_add;
+    c->syncs_del += sg.d_del;
+    c->syncs_rhs += sg.d_rhs;
+    c->m_i = c->m;
+    c->iter += 1;
+    return AA_OK;
+  }
+  if (sg.exec) {
+    (void)hipGraphExecDestroy(sg.exec);
+    sg.exec = nullptr;
+  }
+  const int64_t a0 = c->syncs_add, d0 = c->syncs_del, r0 = c->syncs_rhs;
+  if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return AA_EHIP;
+  const aa_status s = step_enqueue(c, x, g, x_next);
+  hipGraph_t gr = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->stream, &gr);
+  if (s != AA_OK || e != hipSuccess || !gr) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return s != AA_OK ? s : AA_EHIP;
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(gr);
+  if (ei != hipSuccess) return AA_EHIP;
+  sg.exec = exec;
+  sg.x = x;
+  sg.g = g;
+  sg.xn = x_next;
+  sg.d_add = c->syncs_add - a0;
+  sg.d_del = c->syncs_del - d0;
+  sg.d_rhs = c->syncs_rhs - r0;
+  // the capture recorded the iteration (and advanced the host state); run it
+  return hipGraphLaunch(exec, c->stream) == hipSuccess ? AA_OK : AA_EHIP;
+}
+
+aa_status aa_step(aa_ctx* c, const double* x, const double* g, double* x_next) {
+  if (!c || !x || !g || !x_next || (c->flags & AA_QR_ONLY)) return AA_EINVAL;
+  if (x_next == g) return AA_EINVAL;
+  const bool one_wg = c->d_binst && c->n <= c->fused_max;
+  if (c->graph_on && c->stream && !c->prof_on && !one_wg && c->iter > c->m && c->k == c->m)
+    return step_graph(c, x, g, x_next);
+  return step_enqueue(c, x, g, x_next);
+}
+
+aa_status aa_set_graph(aa_ctx* c, int enable) {
+  if (!c) return AA_EINVAL;
+  if (enable && !c->stream) return AA_EINVAL;  // capture needs a stream of its own
+  c->graph_on = enable != 0;
+  if (!c->graph_on) drop_graphs(c);
   return AA_OK;
 }
 
@@ -690,6 +784,7 @@ aa_status aa_qr_basis(aa_ctx* c, double** dQ, int64_t* ldq) {
 
 aa_status aa_qr_load(aa_ctx* c, int k, const double* dQ, int64_t ldq, const double* hR,
                      const double* hT) {
+  if (c) drop_graphs(c);
   if (!c || k < 0 || k > c->cap || (k > 0 && (!dQ || !hR)) || ldq < c->n) return AA_EINVAL;
   const int cap = c->sm.cap;
   if (k > 0) {
@@ -725,6 +820,7 @@ aa_status aa_qr_load(aa_ctx* c, int k, const double* dQ, int64_t ldq, const doub
 }
 
 aa_status aa_reset(aa_ctx* c) {
+  if (c) drop_graphs(c);
   if (!c) return AA_EINVAL;
   c->iter = 0;
   c->k = 0;
@@ -734,6 +830,7 @@ aa_status aa_reset(aa_ctx* c) {
 
 aa_status aa_destroy(aa_ctx* c) {
   if (!c) return AA_OK;
+  drop_graphs(c);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   delete c;
   return AA_OK;
@@ -774,12 +871,14 @@ aa_status aa_profile_read(aa_ctx* c, int kind, double* ms, int64_t* launches, do
 }
 
 aa_status aa_set_fused_threshold(aa_ctx* c, int64_t n_max) {
+  if (c) drop_graphs(c);
   if (!c || n_max < 0) return AA_EINVAL;
   c->fused_max = n_max;
   return AA_OK;
 }
 
 aa_status aa_set_grid(aa_ctx* c, int stream_max, int gram_max) {
+  if (c) drop_graphs(c);
   if (!c || stream_max < 1 || stream_max > 4096 || gram_max < 1 || gram_max > 4096)
     return AA_EINVAL;
   // every pass publishes (values reduced) x (workgroups) partials; the Gram
