@@ -227,6 +227,59 @@ __device__ void wg_qr_delete(const BInst& I, int variant, int k, L& lds) {
   __syncthreads();
 }
 
+// out = G(u) over one instance by one workgroup.  Each thread evaluates four
+// points per round with all their loads issued before any result is stored
+// (the pointers do not alias), and 32-bit index arithmetic (an instance has
+// far fewer than 2^31 points): the plain per-point loop waits out one memory
+// latency per point.
+__device__ __forceinline__ void wg_stencil(const double* __restrict__ u,
+                                           const double* __restrict__ f,
+                                           double* __restrict__ out, int dim, int64_t s64,
+                                           double ih2, double omega, double c, int64_t n64) {
+  if (n64 >= (int64_t)1 << 30) {
+    for (int64_t p = threadIdx.x; p < n64; p += kWG)
+      out[p] = stencil_point(u, f, dim, s64, ih2, omega, c, p);
+    return;
+  }
+  constexpr int U = 4;
+  const int n = (int)n64, s = (int)s64, s2 = s * s;
+  for (int p0 = threadIdx.x; p0 < n; p0 += U * kWG) {
+    double up[U], nb[U], fp[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int p = p0 + q * kWG;
+      up[q] = nb[q] = fp[q] = 0.0;
+      if (p < n) {
+        const int ix = p % s;
+        up[q] = u[p];
+        fp[q] = f[p];
+        double a = 0.0;
+        if (ix > 0) a += u[p - 1];
+        if (ix < s - 1) a += u[p + 1];
+        if (dim >= 2) {
+          const int iy = (p / s) % s;
+          if (iy > 0) a += u[p - s];
+          if (iy < s - 1) a += u[p + s];
+        }
+        if (dim >= 3) {
+          const int iz = p / s2;
+          if (iz > 0) a += u[p - s2];
+          if (iz < s - 1) a += u[p + s2];
+        }
+        nb[q] = a;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int p = p0 + q * kWG;
+      if (p < n) {
+        const double au = (2.0 * dim * up[q] - nb[q]) * ih2;
+        out[p] = up[q] - omega * (au + c * up[q] * up[q] * up[q] - fp[q]);
+      }
+    }
+  }
+}
+
 // Whether QRDelete with k columns can share its pass with the QRAdd's first
 // (AA_FUSE_DELETE, not MGS; the staged [Q v (f)] must fit the Gram bucket).
 template <bool GRAM, class L>
@@ -316,8 +369,7 @@ __device__ bool wg_front(const BatchArgs& b, const BInst& I, BState& st, L& lds,
   const Small& sm = I.sm;
   if (!b.og && I.dim > 0 && !st.g_valid) {
     const double ih2 = 1.0 / (I.h * I.h);
-    for (int64_t p = tid; p < I.n; p += kWG)
-      I.g[p] = stencil_point(x, I.f, I.dim, I.s, ih2, I.omega, I.c, p);
+    wg_stencil(x, I.f, I.g, I.dim, I.s, ih2, I.omega, I.c, I.n);
     __syncthreads();
     st.g_evals += 1;
   }
@@ -457,8 +509,7 @@ __device__ double wg_candidate(const BatchArgs& b, const BInst& I, const BState&
   });
   __syncthreads();
   const double ih2 = 1.0 / (I.h * I.h);
-  for (int64_t p = threadIdx.x; p < I.n; p += kWG)
-    I.gc[p] = stencil_point(I.xc, I.f, I.dim, I.s, ih2, I.omega, I.c, p);
+  wg_stencil(I.xc, I.f, I.gc, I.dim, I.s, ih2, I.omega, I.c, I.n);
   __syncthreads();
   return beta;
 }
