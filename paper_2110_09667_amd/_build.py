@@ -58,5 +58,26 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     return LIB_PATH
 
 
+EXAMPLE_SRC = os.path.join(HERE, "examples", "aa_example.c")
+EXAMPLE_BIN = os.path.join(HERE, "examples", "aa_example")
+
+
+def build_example(verbose: bool = False) -> str:
+    """Compile the plain-C example that drives the C ABI (links libaa.so)."""
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if not cc:
+        raise RuntimeError("no C compiler found for the C-ABI example")
+    rocm = os.path.dirname(os.path.dirname(hipcc()))
+    cmd = [cc, "-std=c11", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__",
+           f"-I{os.path.join(rocm, 'include')}", f"-I{os.path.join(os.path.dirname(HERE), 'include')}",
+           EXAMPLE_SRC, f"-L{HERE}", "-laa", f"-L{os.path.join(rocm, 'lib')}", "-lamdhip64",
+           "-Wl,-rpath,$ORIGIN/..", f"-Wl,-rpath,{os.path.join(rocm, 'lib')}", "-o", EXAMPLE_BIN]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    return EXAMPLE_BIN
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_example(verbose=True))
