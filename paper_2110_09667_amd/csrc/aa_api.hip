@@ -335,7 +335,11 @@ aa_status qr_add_impl(aa_ctx* c, const double* v, const double* f = nullptr,
   return AA_OK;
 }
 
-aa_status qr_delete_impl(aa_ctx* c) {
+// refresh_next: a QRAdd follows (inside aa_step), which recomputes the last
+// row of ICWY's T from its first reduction before anything reads it, so the
+// Gram leaves the last rotated column out (at m = 50: 48 columns, 6 MFMA block
+// pairs per 4 rows instead of 10).  The standalone QRDelete refreshes all of T.
+aa_status qr_delete_impl(aa_ctx* c, bool refresh_next) {
   const int k = c->k;
   if (k <= 0) return AA_ESTATE;
   if (k == 1) {
@@ -345,16 +349,18 @@ aa_status qr_delete_impl(aa_ctx* c) {
   hipError_t e = timed(c, AA_K_GIVENS, 0, [&] { return launch_givens(c->sm, k, c->stream); });
   if (e != hipSuccess) return AA_EHIP;
   const bool gram = c->variant == AA_ICWY;
-  RotArgs r{c->Q, c->ldq, c->n, k, c->sm.givens, gram ? 1 : 0};
+  const int drop = gram && refresh_next ? 1 : 0;
+  RotArgs r{c->Q, c->ldq, c->n, k, c->sm.givens, gram ? 1 : 0, nullptr, nullptr, 0, drop};
+  const int ng = gram_cols(r);  // columns of the Gram
   int gmax = c->grid_stream_max;
-  if (gram) {  // (k-1)(k-2)/2 pair sums per workgroup must fit the partials
-    const int64_t pairs = (int64_t)(k - 1) * (k - 2) / 2;
+  if (gram) {  // ng(ng-1)/2 pair sums per workgroup must fit the partials
+    const int64_t pairs = (int64_t)ng * (ng - 1) / 2;
     const int64_t cap = pairs > 0 ? (int64_t)kPartials / pairs : c->grid_gram_max;
     gmax = (int)(c->grid_gram_max < cap ? c->grid_gram_max : cap);
   }
   const int G = grid_rows(c, gmax);
   e = timed(c, AA_K_ROTATE, 2 * k - 1,
-            [&] { return launch_rotate(r, c->sm, tail(TAIL_GRAM, k - 1), G, c->stream); });
+            [&] { return launch_rotate(r, c->sm, tail(TAIL_GRAM, ng), G, c->stream); });
   if (e != hipSuccess) return AA_EHIP;
   if (gram) c->syncs_del += 1;
   c->k = k - 1;
@@ -640,7 +646,7 @@ static aa_status step_enqueue(aa_ctx* c, const double* x, const double* g,
     // QRDelete + QRAdd of Delta f_{i-1} with their first reductions merged
     s = fused_delete_add(c, c->W, fuse_rhs ? c->f_prev : nullptr, &rhs_done);
   } else {
-    if (i > m) s = qr_delete_impl(c);  // Alg. 2: QRDelete when the window is full
+    if (i > m) s = qr_delete_impl(c, true);  // Alg. 2: QRDelete when the window is full
     if (s == AA_OK)  // Alg. 2: QRAdd of Delta f_{i-1} (optionally also R gamma = Q^T f_i)
       s = qr_add_impl(c, c->W, fuse_rhs ? c->f_prev : nullptr, &rhs_done);
   }
@@ -748,7 +754,7 @@ aa_status aa_qr_add(aa_ctx* c, const double* v) {
 
 aa_status aa_qr_delete(aa_ctx* c) {
   if (!c) return AA_EINVAL;
-  return qr_delete_impl(c);
+  return qr_delete_impl(c, false);
 }
 
 aa_status aa_qr_solve(aa_ctx* c, const double* f, double* gamma) {

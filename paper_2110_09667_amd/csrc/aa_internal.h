@@ -118,7 +118,16 @@ struct RotArgs {         // Givens sweep over k columns (+ ICWY Gram of k-1)
   // Gram only: naug vectors appended after the k-1 rotated columns (v, then
   // f), so the same contraction also yields Q^T v and Q^T f
   const double* v; const double* f; int naug;
+  // Gram only, naug == 0: leave the last rotated column out of the Gram (its
+  // row of T is recomputed by the QRAdd that follows, Alg. 4)
+  int drop_last;
 };
+
+// Columns the Gram of a rotation pass contracts: the k-1 rotated columns
+// (minus the last with drop_last), then the naug appended vectors.
+__host__ __device__ inline int gram_cols(const RotArgs& a) {
+  return a.k - 1 - a.drop_last + a.naug;
+}
 
 struct ScaleArgs { const double* in; double* out; int64_t n; const double* R; int kk; int cap; };
 

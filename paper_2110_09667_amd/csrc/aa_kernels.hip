@@ -134,17 +134,26 @@ __global__ __launch_bounds__(kWG) void k_rotate(RotArgs a, Small sm) {
 // WAVES waves per workgroup: wide Gram staging (KMAX = 64 needs 25 KiB per
 // wave) uses two-wave workgroups so that three of them share a compute unit
 // (six waves) instead of one four-wave workgroup.
+// Load depth of the rotation in the 64-column kernel: its staging leaves at
+// most six waves per compute unit, so each lane keeps this many column loads
+// in flight (measured at n = 2^26, k = 63: 30.2 ms with 8, 26.5 with 16,
+// 25.4 with 32).
+#ifndef AA_ROT_CH_WIDE
+#define AA_ROT_CH_WIDE 32
+#endif
+constexpr int kRotChWide = AA_ROT_CH_WIDE;
+
 template <int KMAX, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_rotate_gram(RotArgs a, Small sm) {
-  // staging rows, then the per-wave pair sums: gram_lds_doubles(k - 1 + naug, WAVES)
+  // staging rows, then the per-wave pair sums: gram_lds_doubles(gram_cols(a), WAVES)
   extern __shared__ double s_buf[];
   __shared__ double s_c[KMAX], s_s[KMAX];
-  const int na = a.k - 1 + a.naug, np = na * (na - 1) / 2;
+  const int na = gram_cols(a), np = na * (na - 1) / 2;
   givens_coefs(a, sm.cap, s_c, s_s, KMAX);
   __syncthreads();
   v4d acc[GramShape<KMAX>::NBP];
-  rotate_gram_body<KMAX, 64 * WAVES>(a, s_c, s_s, blockIdx.x, gridDim.x, s_buf,
-                                     gram_stride(na), acc);
+  rotate_gram_body<KMAX, 64 * WAVES, (KMAX >= 64 ? kRotChWide : kRotCh)>(
+      a, s_c, s_s, blockIdx.x, gridDim.x, s_buf, gram_stride(na), acc);
   __syncthreads();  // the staging area becomes the per-wave pair accumulators
   gram_store<KMAX>(acc, s_buf + (threadIdx.x >> 6) * np, na);
   __syncthreads();
@@ -155,6 +164,61 @@ __global__ __launch_bounds__(64 * WAVES) void k_rotate_gram(RotArgs a, Small sm)
     for (int w = 1; w < WAVES; ++w) s += s_buf[w * np + c];
     sm.partials[(size_t)c * G + b] = s;
   }
+}
+
+// 33 to 64 staged columns with the half-width staging (rotate_gram_split_body):
+// four-wave workgroups, 64 x 33 doubles of LDS per wave, later reused for the
+// per-wave pair sums.
+#ifndef AA_ROT_CH_SPLIT
+#define AA_ROT_CH_SPLIT 8
+#endif
+constexpr int kRotChSplit = AA_ROT_CH_SPLIT;
+// The two-wave 64-column kernel stages 64 x gram_stride(na) doubles per wave:
+// up to na = 53 three of its workgroups (six waves) share a compute unit's
+// 160 KiB, beyond that only two (four waves, one per SIMD, so the MFMA phase
+// of a tile cannot overlap another wave's loads).  From na = 54 on the
+// half-staging kernel (eight waves) is faster: at n = 2^26, 63 columns,
+// 17.5 ms instead of 25.5; at 48-49 columns it is 10-17 % slower.
+constexpr int kGramSplitMin = 54;
+
+__host__ __device__ constexpr int gram_split_lds_doubles(int na) {
+  return kWaves * 64 * kHalfStride > kWaves * (na * (na - 1) / 2)
+             ? kWaves * 64 * kHalfStride
+             : kWaves * (na * (na - 1) / 2);
+}
+
+__global__ __launch_bounds__(kWG) void k_rotate_gram_split(RotArgs a, Small sm) {
+  extern __shared__ double s_buf[];
+  __shared__ double s_c[64], s_s[64];
+  const int na = gram_cols(a), np = na * (na - 1) / 2;
+  givens_coefs(a, sm.cap, s_c, s_s, 64);
+  __syncthreads();
+  v4d acc[10];
+  rotate_gram_split_body<kWG, kRotChSplit>(a, s_c, s_s, blockIdx.x, gridDim.x, s_buf, acc);
+  __syncthreads();  // the staging area becomes the per-wave pair accumulators
+  gram_store<64>(acc, s_buf + (threadIdx.x >> 6) * np, na);
+  publish(sm, np, s_buf, np);
+}
+
+// ICWY QRDelete for at most NAMAX (4 or 8) staged columns: rotation and strict
+// lower Gram on the vector units (rotate_gram_small_body), per-wave pair sums
+// by one butterfly reduction, then the usual per-workgroup partials.
+constexpr int kGramSmall = 8;
+
+template <int NAMAX>
+__global__ __launch_bounds__(kWG) void k_rotate_gram_small(RotArgs a, Small sm) {
+  constexpr int NR = NAMAX == 4 ? 8 : 32;  // NAMAX (NAMAX - 1) / 2 pairs, padded
+  __shared__ double s_c[NAMAX], s_s[NAMAX];
+  __shared__ double s_acc[kWaves * NR];
+  const int na = gram_cols(a), np = na * (na - 1) / 2;
+  givens_coefs(a, sm.cap, s_c, s_s, NAMAX);
+  __syncthreads();
+  double acc[NR];
+  rotate_gram_small_body<NAMAX>(a, s_c, s_s, blockIdx.x, gridDim.x, acc);
+  const double r = multi_reduce<NR>(acc);
+  const int lane = threadIdx.x & 63;
+  if (lane < NR) s_acc[(threadIdx.x >> 6) * NR + lane] = r;
+  publish(sm, np, s_acc, NR);
 }
 
 __global__ __launch_bounds__(kWG) void k_scale(ScaleArgs a) {
@@ -272,20 +336,29 @@ hipError_t launch_rotate(const RotArgs& a, const Small& sm, const Tail& t, int g
                          hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
   if (a.gram) {
-    // dynamic LDS sized for the live columns: fewer columns, more resident
-    // workgroups per compute unit
-    const int na = a.k - 1 + a.naug;  // staged columns
-    if (na <= 16) {
+    // The kernel instance must hold every rotated column (its Givens
+    // coefficient arrays) and every staged one: w = max(k - 1, Gram columns).
+    // The Gram's own column count na sizes the dynamic LDS (fewer columns,
+    // more resident workgroups) and picks the 64-column variant.
+    const int na = gram_cols(a), w = a.k - 1 + a.naug;
+    if (w <= 4) {
+      hipLaunchKernelGGL(k_rotate_gram_small<4>, dim3(grid), dim3(kWG), 0, st, a, sm);
+    } else if (w <= kGramSmall) {
+      hipLaunchKernelGGL(k_rotate_gram_small<kGramSmall>, dim3(grid), dim3(kWG), 0, st, a, sm);
+    } else if (w <= 16) {
       const size_t lds = sizeof(double) * (size_t)gram_lds_doubles(na, kWaves);
       hipLaunchKernelGGL((k_rotate_gram<16, kWaves>), dim3(grid), dim3(kWG), lds, st, a, sm);
-    } else if (na <= 32) {
+    } else if (w <= 32) {
       const size_t lds = sizeof(double) * (size_t)gram_lds_doubles(na, kWaves);
       hipLaunchKernelGGL((k_rotate_gram<32, kWaves>), dim3(grid), dim3(kWG), lds, st, a, sm);
-    } else if (na <= 64) {
+    } else if (w <= 64 && na < kGramSplitMin) {
       const size_t lds = sizeof(double) * (size_t)gram_lds_doubles(na, 2);
       hipLaunchKernelGGL((k_rotate_gram<64, 2>), dim3(grid), dim3(128), lds, st, a, sm);
+    } else if (w <= 64) {  // na >= kGramSplitMin > 32, as the half staging needs
+      const size_t lds = sizeof(double) * (size_t)gram_split_lds_doubles(na);
+      hipLaunchKernelGGL(k_rotate_gram_split, dim3(grid), dim3(kWG), lds, st, a, sm);
     } else {
-      return hipErrorInvalidValue;  // at most 64 staged columns
+      return hipErrorInvalidValue;  // at most 64 rotated or staged columns
     }
     return launch_finalize(sm, t, na * (na - 1) / 2, grid, st);
   }

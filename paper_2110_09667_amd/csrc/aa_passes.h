@@ -456,33 +456,35 @@ __device__ inline void givens_coefs(const RotArgs& a, int cap, double* s_c, doub
 // Per row: x <- q_0; for j < k-1: (q_j, x) <- (c_j x + s_j q_{j+1},
 // -s_j x + c_j q_{j+1}) -- rotation j of QRDelete applied to columns j, j+1
 // of Q, in the order the rotations were generated.  The sweep streams the
-// columns in chunks of kRotCh with the next chunk's loads issued before the
+// columns in chunks of CH with the next chunk's loads issued before the
 // current chunk's stores (registers hold two chunks, not the whole row).
 // Each rotated value is also passed to emit(j, value) (the ICWY Gram stages it).
+// CH is the number of loads a lane keeps in flight: kernels that run few waves
+// per SIMD (wide Gram staging) need a deeper chunk to keep HBM busy.
 constexpr int kRotCh = 8;
 
-template <class Emit>
+template <int CH = kRotCh, class Emit>
 __device__ __forceinline__ void rotate_row(const RotArgs& a, int64_t row, bool valid,
                                            const double* s_c, const double* s_s, Emit&& emit) {
   const int kk = a.k - 1;
   const double* qrow = a.Q + row;
   double* qw = a.Q + row;
   double x = valid ? ld1(qrow) : 0.0;
-  double nxt[kRotCh];
+  double nxt[CH];
 #pragma unroll
-  for (int c = 0; c < kRotCh; ++c)
+  for (int c = 0; c < CH; ++c)
     nxt[c] = (valid && 1 + c < a.k) ? ld1(qrow + (int64_t)(1 + c) * a.ldq) : 0.0;
-  for (int j0 = 0; j0 < kk; j0 += kRotCh) {
-    double cur[kRotCh];
+  for (int j0 = 0; j0 < kk; j0 += CH) {
+    double cur[CH];
 #pragma unroll
-    for (int c = 0; c < kRotCh; ++c) cur[c] = nxt[c];
+    for (int c = 0; c < CH; ++c) cur[c] = nxt[c];
 #pragma unroll
-    for (int c = 0; c < kRotCh; ++c) {
-      const int jn = j0 + kRotCh + 1 + c;
+    for (int c = 0; c < CH; ++c) {
+      const int jn = j0 + CH + 1 + c;
       nxt[c] = (valid && jn < a.k) ? ld1(qrow + (int64_t)jn * a.ldq) : 0.0;
     }
 #pragma unroll
-    for (int c = 0; c < kRotCh; ++c) {
+    for (int c = 0; c < CH; ++c) {
       const int j = j0 + c;
       if (j < kk) {
         const double y = cur[c];
@@ -584,7 +586,10 @@ __host__ __device__ constexpr int gram_lds_doubles(int kk, int waves = kWaves) {
 // kk.  Operand layout of that instruction: lane l supplies A[l % 16][l / 16]
 // and B[l / 16][l % 16]; lane l, register r of the result holds
 // D[l / 16 + 4 r][l % 16].  Accumulators stay in registers across all tiles.
-template <int KMAX, int WG = kWG>
+// In the 64-column instance, block pairs whose row block lies wholly past the
+// live columns are skipped (their accumulators stay zero; the narrower
+// instances always have every block live).  CH is the rotation's load depth.
+template <int KMAX, int WG = kWG, int CH = kRotCh>
 __device__ inline void rotate_gram_body(const RotArgs& a, const double* s_c, const double* s_s,
                                         int64_t t0, int64_t ts, double* stage_all, int kp,
                                         v4d (&acc)[GramShape<KMAX>::NBP]) {
@@ -595,17 +600,20 @@ __device__ inline void rotate_gram_body(const RotArgs& a, const double* s_c, con
 #pragma unroll
   for (int p = 0; p < S::NBP; ++p) acc[p] = v4d{0.0, 0.0, 0.0, 0.0};
   const int64_t ntiles = (a.n + WG - 1) / WG;
-  const int kk = a.k - 1, na = kk + a.naug;
+  const int kk = a.k - 1, na = gram_cols(a);
   bool live[S::NB];
 #pragma unroll
   for (int b = 0; b < S::NB; ++b) live[b] = b * 16 + li < na;
+  const int nbl = (na + 15) / 16;  // blocks holding a live column
   for (int64_t tile = t0; tile < ntiles; tile += ts) {
     const int64_t row = tile * WG + threadIdx.x;
     const bool valid = row < a.n;
     double* srow = stage + lane * kp;
     if (a.naug > 0) srow[kk] = valid ? ld1(a.v + row) : 0.0;
     if (a.naug > 1) srow[kk + 1] = valid ? ld1(a.f + row) : 0.0;
-    rotate_row(a, row, valid, s_c, s_s, [&](int j, double v) { srow[j] = v; });
+    rotate_row<CH>(a, row, valid, s_c, s_s, [&](int j, double v) {
+      if (j < na) srow[j] = v;
+    });
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -619,7 +627,186 @@ __device__ inline void rotate_gram_body(const RotArgs& a, const double* s_c, con
       for (int bi = 0; bi < S::NB; ++bi)
 #pragma unroll
         for (int bj = 0; bj <= bi; ++bj, ++p)
-          acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[bi], v[bj], acc[p], 0, 0, 0);
+          if (KMAX < 64 || bi < nbl)
+            acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[bi], v[bj], acc[p], 0, 0, 0);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// Small windows (at most NAMAX staged columns): the same rotation and strict
+// lower Gram without matrix cores.  Each lane takes a pair of rows (16-byte
+// loads; an odd last row alone), loads its k columns at once, rotates them in
+// registers and accumulates the pair products of the staged values z (the kk
+// rotated columns, then v and f when a.naug > 0) in acc[i (i - 1) / 2 + j],
+// j < i < na.  A 16 x 16 x 4 MFMA block spends 256 multiply-adds per row
+// whatever the live columns; here a row costs na (na - 1) / 2, and FP64 MFMA
+// runs no faster than the vector units.
+template <int NAMAX, int NR, bool PAIR>
+__device__ __forceinline__ void gram_small_rows(const RotArgs& a, const double* s_c,
+                                                const double* s_s, int64_t row,
+                                                double (&acc)[NR]) {
+  const int kk = a.k - 1, na = gram_cols(a);
+  auto load = [&](const double* p) -> f64x2 {
+    if constexpr (PAIR) return ld2v(reinterpret_cast<const double2*>(p));
+    else return f64x2{ld1(p), 0.0};
+  };
+  auto load_aug = [&](const double* p) -> f64x2 {
+    if constexpr (PAIR) return f64x2{ld1(p), ld1(p + 1)};  // v, f: no alignment assumed
+    else return f64x2{ld1(p), 0.0};
+  };
+  f64x2 q[NAMAX + 1];
+#pragma unroll
+  for (int j = 0; j <= NAMAX; ++j)
+    q[j] = j <= kk ? load(a.Q + row + (int64_t)j * a.ldq) : f64x2{0.0, 0.0};
+  const f64x2 v0 = a.naug > 0 ? load_aug(a.v + row) : f64x2{0.0, 0.0};
+  const f64x2 v1 = a.naug > 1 ? load_aug(a.f + row) : f64x2{0.0, 0.0};
+  f64x2 z[NAMAX];
+  f64x2 x = q[0];
+#pragma unroll
+  for (int j = 0; j < NAMAX; ++j) {
+    if (j < kk) {
+      const f64x2 y = q[j + 1];
+      const double cj = s_c[j], sj = s_s[j];
+      f64x2 qn;
+      qn.x = cj * x.x + sj * y.x;
+      qn.y = cj * x.y + sj * y.y;
+      x.x = -sj * x.x + cj * y.x;
+      x.y = -sj * x.y + cj * y.y;
+      double* qw = a.Q + row + (int64_t)j * a.ldq;
+      if constexpr (PAIR) st2v_stream(qn, qw);
+      else st1_stream(qn.x, qw);
+      z[j] = qn;
+    } else {
+      z[j] = j == kk ? v0 : (j == kk + 1 ? v1 : f64x2{0.0, 0.0});
+    }
+  }
+  int p = 0;
+#pragma unroll
+  for (int i = 1; i < NAMAX; ++i)
+#pragma unroll
+    for (int j = 0; j < i; ++j, ++p)
+      if (i < na) acc[p] += z[i].x * z[j].x + z[i].y * z[j].y;
+}
+
+template <int NAMAX, int NR>
+__device__ inline void rotate_gram_small_body(const RotArgs& a, const double* s_c,
+                                              const double* s_s, int64_t t0, int64_t ts,
+                                              double (&acc)[NR]) {
+  static_assert(NAMAX * (NAMAX - 1) / 2 <= NR, "pair accumulators");
+#pragma unroll
+  for (int p = 0; p < NR; ++p) acc[p] = 0.0;
+  const int64_t npair = a.n / 2;
+  for (int64_t pr = t0 * kWG + threadIdx.x; pr < npair; pr += ts * kWG)
+    gram_small_rows<NAMAX, NR, true>(a, s_c, s_s, 2 * pr, acc);
+  if ((a.n & 1) && t0 == 0 && threadIdx.x == 0)
+    gram_small_rows<NAMAX, NR, false>(a, s_c, s_s, a.n - 1, acc);
+}
+
+// 33 to 64 staged columns with half the staging.  The rotation sweep of a row
+// is resumed in two halves (rotations 0..31, then 32..kk-1), each half staged
+// in a 64-row x 32-column LDS tile (row stride kHalfStride).  After the first
+// half each lane keeps its MFMA operands of blocks 0 and 1 for all 16 row
+// quads of the tile in registers (32 doubles), so the second half can pair
+// blocks 2 and 3 with them.  Half the LDS of rotate_gram_body<64> per wave:
+// twice the waves per compute unit.  Same pairs and accumulator order
+// (p = bi (bi + 1) / 2 + bj), so gram_store<64> applies.
+constexpr int kHalfStride = 33;
+
+template <int WG, int CH>
+__device__ inline void rotate_gram_split_body(const RotArgs& a, const double* s_c,
+                                              const double* s_s, int64_t t0, int64_t ts,
+                                              double* stage_all, v4d (&acc)[10]) {
+  static_assert(32 % CH == 0, "the halves are whole chunks");
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  double* stage = stage_all + w * 64 * kHalfStride;
+  double* srow = stage + lane * kHalfStride;
+#pragma unroll
+  for (int p = 0; p < 10; ++p) acc[p] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int64_t ntiles = (a.n + WG - 1) / WG;
+  const int kk = a.k - 1, na = gram_cols(a);  // 32 < na <= 64
+  const bool live2 = 32 + li < na, live3 = 48 + li < na, blk3 = na > 48;
+  for (int64_t tile = t0; tile < ntiles; tile += ts) {
+    const int64_t row = tile * WG + threadIdx.x;
+    const bool valid = row < a.n;
+    const double* qrow = a.Q + row;
+    double* qw = a.Q + row;
+    const double av = (valid && a.naug > 0) ? ld1(a.v + row) : 0.0;
+    const double af = (valid && a.naug > 1) ? ld1(a.f + row) : 0.0;
+    double x = valid ? ld1(qrow) : 0.0;
+    double nxt[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+      nxt[c] = (valid && 1 + c < a.k) ? ld1(qrow + (int64_t)(1 + c) * a.ldq) : 0.0;
+    // rotations jb .. min(je, kk) - 1, rotated column j staged at j - base
+    auto sweep = [&](int jb, int je, int base) {
+      for (int j0 = jb; j0 < je && j0 < kk; j0 += CH) {
+        double cur[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) cur[c] = nxt[c];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          const int jn = j0 + CH + 1 + c;
+          nxt[c] = (valid && jn < a.k) ? ld1(qrow + (int64_t)jn * a.ldq) : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          const int j = j0 + c;
+          if (j < kk) {
+            const double y = cur[c];
+            const double cj = s_c[j], sj = s_s[j];
+            const double qn = cj * x + sj * y;
+            x = -sj * x + cj * y;
+            if (valid) st1_stream(qn, qw + (int64_t)j * a.ldq);
+            if (j < na) srow[j - base] = valid ? qn : 0.0;
+          }
+        }
+      }
+    };
+    // first half: columns 0..31 (the augmented v, f when they fall there)
+    sweep(0, 32, 0);
+    if (a.naug > 0 && kk < 32) srow[kk] = av;
+    if (a.naug > 1 && kk + 1 < 32) srow[kk + 1] = af;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double h0[16], h1[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int r = 4 * q + lk;
+      h0[q] = stage[r * kHalfStride + li];
+      h1[q] = stage[r * kHalfStride + 16 + li];
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(h0[q], h0[q], acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(h1[q], h0[q], acc[1], 0, 0, 0);
+      acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(h1[q], h1[q], acc[2], 0, 0, 0);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // second half: columns 32 .. na-1
+    sweep(32, 64, 32);
+    if (a.naug > 0 && kk >= 32) srow[kk - 32] = av;
+    if (a.naug > 1 && kk + 1 >= 32) srow[kk - 31] = af;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int r = 4 * q + lk;
+      const double v2 = live2 ? stage[r * kHalfStride + li] : 0.0;
+      const double v3 = live3 ? stage[r * kHalfStride + 16 + li] : 0.0;
+      acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(v2, h0[q], acc[3], 0, 0, 0);
+      acc[4] = __builtin_amdgcn_mfma_f64_16x16x4f64(v2, h1[q], acc[4], 0, 0, 0);
+      acc[5] = __builtin_amdgcn_mfma_f64_16x16x4f64(v2, v2, acc[5], 0, 0, 0);
+      if (blk3) {
+        acc[6] = __builtin_amdgcn_mfma_f64_16x16x4f64(v3, h0[q], acc[6], 0, 0, 0);
+        acc[7] = __builtin_amdgcn_mfma_f64_16x16x4f64(v3, h1[q], acc[7], 0, 0, 0);
+        acc[8] = __builtin_amdgcn_mfma_f64_16x16x4f64(v3, v2, acc[8], 0, 0, 0);
+        acc[9] = __builtin_amdgcn_mfma_f64_16x16x4f64(v3, v3, acc[9], 0, 0, 0);
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();

@@ -135,13 +135,17 @@ def test_qr_add_wide_bases(variant, k):
     compare_qr(ctx, ref, tol)
 
 
-@pytest.mark.parametrize("k", [5, 12, 20, 33, 47, 64])
+@pytest.mark.parametrize("k", [2, 5, 9, 10, 12, 20, 33, 34, 49, 50, 54, 55, 64])
 def test_icwy_T_refresh_on_nonorthonormal_basis(k):
     """ICWY's T refresh after QRDelete is a Gram matrix of the rotated basis.
     On an orthonormal basis its strict lower part is ~1e-15 everywhere, which
     would hide a misplaced entry; an MGS basis of a kappa = 1e12 matrix has
     lost orthogonality (~1e-4), so every entry of T is checked for real.
-    Covers the 16, 32 and 64-column Gram blocks."""
+    k - 1 columns are rotated and contracted: the vector-unit Gram (at most 8,
+    k = 2 leaving a single column and no pair), the 16- and 32-column MFMA
+    blocks, the two-wave 64-column kernel with its last 16-column block empty
+    (k = 34, 49) or holding one column (k = 50, 54), and the half-staging
+    kernel from 54 columns on (k = 55, 64)."""
     import torch
     device()
     aa = aa_mod()
@@ -491,6 +495,45 @@ def test_aa_nonlinear3d_full_size_m20_properties(variant):
     FtR = torch.stack([torch.dot(F[:, j], res) for j in range(m)])
     opt = torch.linalg.norm(FtR) / (torch.linalg.norm(F) * torch.linalg.norm(f))
     assert opt.item() <= 1e-10
+
+
+@pytest.mark.parametrize("m", [6, 10, 11, 19, 35, 50, 55, 56, 64])
+def test_icwy_step_keeps_T_invariant(m):
+    """Inside aa_step the ICWY QRDelete leaves the newest rotated column out of
+    its Gram refresh: the QRAdd that follows recomputes that row of T from its
+    first reduction (Alg. 4) before anything reads it.  After every recycled
+    iteration, rows 0..K-2 of T must equal the strict lower part of Q^T Q of
+    the current basis (row K-1 waits for the next add), whichever Gram kernel
+    ran: m = 6 and 10 the vector-unit ones, 11 and 19 the 16- and 32-column
+    MFMA blocks, 35/50/55 the two-wave 64-column kernel (last block empty or
+    not), 56 and 64 the half-staging kernel.  (The iterates of long windows on
+    this problem are too ill-conditioned for an iterate comparison: two exact
+    QR variants in FP64 part by 1e-5 within 60 iterations.)  The standalone
+    QRDelete keeps refreshing every row (test_icwy_T_refresh_on_nonorthonormal_basis)."""
+    import torch
+    device()
+    prob = W.poisson1d()
+    aa = aa_mod()
+    ctx = aa.AAContext(prob.n, m, "icwy")
+    ctx.set_fused_threshold(0)  # grid-wide passes
+    f_d = to_dev(prob.f)
+    x = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+    g = torch.empty_like(x)
+    checked = 0
+    for i in range(m + 4):
+        aa.aa_problem_apply(prob.d, prob.s, prob.h, prob.omega, prob.c, f_d, x, g)
+        ctx.step(x, g, x)
+        if i <= m:
+            continue
+        R, T, K = ctx.get_qr()
+        assert K == m
+        Q = ctx.basis(K)
+        G = (Q.T @ Q).cpu().numpy()
+        lower = np.tril(T[:K - 1, :K - 1], -1) - np.tril(G[:K - 1, :K - 1], -1)
+        assert np.abs(lower).max() <= 1e-13, (i, np.abs(lower).max())
+        assert np.abs(np.diag(T)[:K] - 1.0).max() == 0.0
+        checked += 1
+    assert checked == 3 and ctx.info().status == 0
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
