@@ -98,6 +98,21 @@ __global__ __launch_bounds__(kWG) void k_dots(DotsArgs a, Small sm) {
   publish(sm, dots_nred(a), s_acc, kMaxRed);
 }
 
+// Block dot products with per-lane register accumulators (dots_reg_body):
+// KQ-column buckets, one or two right-hand sides, no z block.
+#ifndef AA_DOTS_REG
+#define AA_DOTS_REG 1
+#endif
+template <int KQ, int NR>
+__global__ __launch_bounds__(kWG) void k_dots_reg(DotsArgs a, Small sm) {
+  constexpr int STR = NR * KQ + 1;
+  __shared__ double s_acc[kWaves * STR];
+  lds_zero(s_acc, kWaves * STR);
+  __syncthreads();
+  dots_reg_body<KQ, NR>(a, blockIdx.x, gridDim.x, s_acc + (threadIdx.x >> 6) * STR);
+  publish(sm, dots_nred(a), s_acc, STR);
+}
+
 __global__ __launch_bounds__(kWG) void k_update(UpdArgs a, Small sm) {
   __shared__ double s_c1[kMaxCols], s_c2[kMaxCols], s_s[kMaxCols];
   __shared__ double s_acc[kWaves * 4];
@@ -301,7 +316,23 @@ static hipError_t launch_finalize(const Small& sm, const Tail& t, int nred, int 
 hipError_t launch_dots(const DotsArgs& a, const Small& sm, const Tail& t, int grid,
                        hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
-  hipLaunchKernelGGL(k_dots, dim3(grid), dim3(kWG), 0, st, a, sm);
+  const int nq = a.nx > a.ny ? a.nx : a.ny;
+  if (AA_DOTS_REG && a.nz == 0 && a.ny == 0 && nq <= 8)
+    hipLaunchKernelGGL((k_dots_reg<8, 1>), dim3(grid), dim3(kWG), 0, st, a, sm);
+  else if (AA_DOTS_REG && a.nz == 0 && a.ny == 0 && nq <= 16)
+    hipLaunchKernelGGL((k_dots_reg<16, 1>), dim3(grid), dim3(kWG), 0, st, a, sm);
+  else if (AA_DOTS_REG && a.nz == 0 && a.ny == 0 && nq <= 32)
+    hipLaunchKernelGGL((k_dots_reg<32, 1>), dim3(grid), dim3(kWG), 0, st, a, sm);
+  else if (AA_DOTS_REG && a.nz == 0 && a.ny == 0 && nq <= 64)
+    hipLaunchKernelGGL((k_dots_reg<64, 1>), dim3(grid), dim3(kWG), 0, st, a, sm);
+  else if (AA_DOTS_REG && a.nz == 0 && nq <= 8)
+    hipLaunchKernelGGL((k_dots_reg<8, 2>), dim3(grid), dim3(kWG), 0, st, a, sm);
+  else if (AA_DOTS_REG && a.nz == 0 && nq <= 16)
+    hipLaunchKernelGGL((k_dots_reg<16, 2>), dim3(grid), dim3(kWG), 0, st, a, sm);
+  else if (AA_DOTS_REG && a.nz == 0 && nq <= 32)
+    hipLaunchKernelGGL((k_dots_reg<32, 2>), dim3(grid), dim3(kWG), 0, st, a, sm);
+  else
+    hipLaunchKernelGGL(k_dots, dim3(grid), dim3(kWG), 0, st, a, sm);
   return launch_finalize(sm, t, a.nx + a.ny + a.nz + (a.xx ? 1 : 0), grid, st);
 }
 

@@ -251,6 +251,59 @@ __device__ inline void dots_body(const DotsArgs& a, int64_t t0, int64_t ts, doub
   });
 }
 
+// Register-accumulated block dot products for nz == 0, at most KQ columns and
+// NR right-hand sides (x, and y when NR == 2): each lane keeps its running
+// sums of every (column, right-hand side) pair over all of its tiles, and each
+// wave reduces them once at the end (one NR KQ-wide butterfly) instead of
+// once per column group and tile.  Leaves the wave's sums in acc in
+// dots_body's layout (x block, y block, then x^T x).
+template <int KQ, int NR>
+__device__ inline void dots_reg_body(const DotsArgs& a, int64_t t0, int64_t ts, double* acc) {
+  constexpr int N = NR * KQ;  // a power of two, at most 64
+  static_assert(N <= 64 && (N & (N - 1)) == 0, "one butterfly per wave");
+  const int lane = threadIdx.x & 63;
+  const int nq = a.nx > a.ny ? a.nx : a.ny;
+  double s[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) s[i] = 0.0;
+  double sxx = 0.0;
+  for_tiles(a.n, t0, ts, [&](int64_t b2, auto full) {
+    constexpr bool F = decltype(full)::value;
+    double2 xv[kPairs], yv[kPairs];
+    ld2<F>(xv, a.x, b2, a.n);
+    if constexpr (NR > 1) ld2<F>(yv, a.y, b2, a.n);
+    if (a.xx) sxx += dot2(xv, xv);
+#pragma unroll
+    for (int j0 = 0; j0 < KQ; j0 += kGroup) {
+      if (j0 < nq) {
+        double2 q[kGroup][kPairs];
+#pragma unroll
+        for (int c = 0; c < kGroup; ++c) {
+          if (j0 + c < nq)
+            ld2<F>(q[c], a.Q + (int64_t)(j0 + c) * a.ldq, b2, a.n);
+          else
+            zero2(q[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < kGroup; ++c) {
+          s[j0 + c] += dot2(q[c], xv);
+          if constexpr (NR > 1) s[KQ + j0 + c] += dot2(q[c], yv);
+        }
+      }
+    }
+  });
+  const double r = multi_reduce<N>(s);  // lane l < N: s[l] over the wave
+  if (lane < N) {
+    const int rh = lane / KQ, j = lane % KQ;
+    if (rh == 0 && j < a.nx) acc[j] = r;
+    if (rh == 1 && j < a.ny) acc[a.nx + j] = r;
+  }
+  if (a.xx) {
+    const double p = wave_sum(sxx);
+    if (lane == 0) acc[a.nx + a.ny] = p;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // vector update out = v - Q c (+ fused dot / norm); DCGS-2 reorthogonalization
 // acc_w[0] += Q_dotcol^T out (if dotcol >= 0); acc_w[inorm] += out^T out
