@@ -99,13 +99,16 @@ __global__ __launch_bounds__(kWG) void k_dots(DotsArgs a, Small sm) {
 }
 
 // Block dot products with per-lane register accumulators (dots_reg_body):
-// KQ-column buckets, one or two right-hand sides, no z block.
+// KQ-column buckets, one to three right-hand sides.
 #ifndef AA_DOTS_REG
 #define AA_DOTS_REG 1
 #endif
+#ifndef AA_DOTS_REG3
+#define AA_DOTS_REG3 AA_DOTS_REG
+#endif
 template <int KQ, int NR>
 __global__ __launch_bounds__(kWG) void k_dots_reg(DotsArgs a, Small sm) {
-  constexpr int STR = NR * KQ + 1;
+  constexpr int STR = NR * KQ + 1;  // nx + ny + nz + xx <= NR KQ + 1
   __shared__ double s_acc[kWaves * STR];
   lds_zero(s_acc, kWaves * STR);
   __syncthreads();
@@ -316,21 +319,31 @@ static hipError_t launch_finalize(const Small& sm, const Tail& t, int nred, int 
 hipError_t launch_dots(const DotsArgs& a, const Small& sm, const Tail& t, int grid,
                        hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
-  const int nq = a.nx > a.ny ? a.nx : a.ny;
-  if (AA_DOTS_REG && a.nz == 0 && a.ny == 0 && nq <= 8)
+  // every vector the counts name must exist
+  if (!a.x || (a.ny > 0 && !a.y) || (a.nz > 0 && !a.z)) return hipErrorInvalidValue;
+  int nq = a.nx > a.ny ? a.nx : a.ny;
+  if (a.nz > nq) nq = a.nz;
+  const int nr = a.nz > 0 ? 3 : (a.ny > 0 ? 2 : 1);  // right-hand sides
+  if (AA_DOTS_REG && nr == 1 && nq <= 8)
     hipLaunchKernelGGL((k_dots_reg<8, 1>), dim3(grid), dim3(kWG), 0, st, a, sm);
-  else if (AA_DOTS_REG && a.nz == 0 && a.ny == 0 && nq <= 16)
+  else if (AA_DOTS_REG && nr == 1 && nq <= 16)
     hipLaunchKernelGGL((k_dots_reg<16, 1>), dim3(grid), dim3(kWG), 0, st, a, sm);
-  else if (AA_DOTS_REG && a.nz == 0 && a.ny == 0 && nq <= 32)
+  else if (AA_DOTS_REG && nr == 1 && nq <= 32)
     hipLaunchKernelGGL((k_dots_reg<32, 1>), dim3(grid), dim3(kWG), 0, st, a, sm);
-  else if (AA_DOTS_REG && a.nz == 0 && a.ny == 0 && nq <= 64)
+  else if (AA_DOTS_REG && nr == 1 && nq <= 64)
     hipLaunchKernelGGL((k_dots_reg<64, 1>), dim3(grid), dim3(kWG), 0, st, a, sm);
-  else if (AA_DOTS_REG && a.nz == 0 && nq <= 8)
+  else if (AA_DOTS_REG && nr == 2 && nq <= 8)
     hipLaunchKernelGGL((k_dots_reg<8, 2>), dim3(grid), dim3(kWG), 0, st, a, sm);
-  else if (AA_DOTS_REG && a.nz == 0 && nq <= 16)
+  else if (AA_DOTS_REG && nr == 2 && nq <= 16)
     hipLaunchKernelGGL((k_dots_reg<16, 2>), dim3(grid), dim3(kWG), 0, st, a, sm);
-  else if (AA_DOTS_REG && a.nz == 0 && nq <= 32)
+  else if (AA_DOTS_REG && nr == 2 && nq <= 32)
     hipLaunchKernelGGL((k_dots_reg<32, 2>), dim3(grid), dim3(kWG), 0, st, a, sm);
+  else if (AA_DOTS_REG3 && nr == 3 && nq <= 8)
+    hipLaunchKernelGGL((k_dots_reg<8, 3>), dim3(grid), dim3(kWG), 0, st, a, sm);
+  else if (AA_DOTS_REG3 && nr == 3 && nq <= 16)
+    hipLaunchKernelGGL((k_dots_reg<16, 3>), dim3(grid), dim3(kWG), 0, st, a, sm);
+  else if (AA_DOTS_REG3 && nr == 3 && nq <= 32)
+    hipLaunchKernelGGL((k_dots_reg<32, 3>), dim3(grid), dim3(kWG), 0, st, a, sm);
   else
     hipLaunchKernelGGL(k_dots, dim3(grid), dim3(kWG), 0, st, a, sm);
   return launch_finalize(sm, t, a.nx + a.ny + a.nz + (a.xx ? 1 : 0), grid, st);

@@ -251,28 +251,40 @@ __device__ inline void dots_body(const DotsArgs& a, int64_t t0, int64_t ts, doub
   });
 }
 
-// Register-accumulated block dot products for nz == 0, at most KQ columns and
-// NR right-hand sides (x, and y when NR == 2): each lane keeps its running
-// sums of every (column, right-hand side) pair over all of its tiles, and each
-// wave reduces them once at the end (one NR KQ-wide butterfly) instead of
-// once per column group and tile.  Leaves the wave's sums in acc in
-// dots_body's layout (x block, y block, then x^T x).
+// Register-accumulated block dot products for at most KQ columns and NR
+// right-hand sides (x; y when NR >= 2; z when NR == 3): each lane keeps its
+// running sums of every (column, right-hand side) pair over all of its tiles,
+// and each wave reduces them once at the end (one KQ-wide butterfly per
+// right-hand side) instead of once per column group and tile.  Leaves the
+// wave's sums in acc in dots_body's layout (x block, y block, z block, then
+// x^T x).
 template <int KQ, int NR>
 __device__ inline void dots_reg_body(const DotsArgs& a, int64_t t0, int64_t ts, double* acc) {
-  constexpr int N = NR * KQ;  // a power of two, at most 64
-  static_assert(N <= 64 && (N & (N - 1)) == 0, "one butterfly per wave");
+  static_assert(KQ <= 64 && (KQ & (KQ - 1)) == 0 && NR >= 1 && NR <= 3, "bucket");
   const int lane = threadIdx.x & 63;
-  const int nq = a.nx > a.ny ? a.nx : a.ny;
-  double s[N];
+  int nq = a.nx > a.ny ? a.nx : a.ny;
+  if (a.nz > nq) nq = a.nz;
+  double s[NR][KQ];
 #pragma unroll
-  for (int i = 0; i < N; ++i) s[i] = 0.0;
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int i = 0; i < KQ; ++i) s[r][i] = 0.0;
   double sxx = 0.0;
   for_tiles(a.n, t0, ts, [&](int64_t b2, auto full) {
     constexpr bool F = decltype(full)::value;
-    double2 xv[kPairs], yv[kPairs];
-    ld2<F>(xv, a.x, b2, a.n);
-    if constexpr (NR > 1) ld2<F>(yv, a.y, b2, a.n);
-    if (a.xx) sxx += dot2(xv, xv);
+    double2 rv[NR][kPairs];
+    // y (z) exists only when ny (nz) > 0: CGS-2 with the folded RHS has x and
+    // z but no y, and its y pointer is null
+    ld2<F>(rv[0], a.x, b2, a.n);
+    if constexpr (NR > 1) {
+      if (a.ny > 0) ld2<F>(rv[1], a.y, b2, a.n);
+      else zero2(rv[1]);
+    }
+    if constexpr (NR > 2) {
+      if (a.nz > 0) ld2<F>(rv[2], a.z, b2, a.n);
+      else zero2(rv[2]);
+    }
+    if (a.xx) sxx += dot2(rv[0], rv[0]);
 #pragma unroll
     for (int j0 = 0; j0 < KQ; j0 += kGroup) {
       if (j0 < nq) {
@@ -285,22 +297,23 @@ __device__ inline void dots_reg_body(const DotsArgs& a, int64_t t0, int64_t ts, 
             zero2(q[c]);
         }
 #pragma unroll
-        for (int c = 0; c < kGroup; ++c) {
-          s[j0 + c] += dot2(q[c], xv);
-          if constexpr (NR > 1) s[KQ + j0 + c] += dot2(q[c], yv);
-        }
+        for (int c = 0; c < kGroup; ++c)
+#pragma unroll
+          for (int r = 0; r < NR; ++r) s[r][j0 + c] += dot2(q[c], rv[r]);
       }
     }
   });
-  const double r = multi_reduce<N>(s);  // lane l < N: s[l] over the wave
-  if (lane < N) {
-    const int rh = lane / KQ, j = lane % KQ;
-    if (rh == 0 && j < a.nx) acc[j] = r;
-    if (rh == 1 && j < a.ny) acc[a.nx + j] = r;
+  const int cnt[3] = {a.nx, a.ny, a.nz};
+  int off = 0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const double v = multi_reduce<KQ>(s[r]);  // lane l < KQ: column l over the wave
+    if (lane < cnt[r]) acc[off + lane] = v;
+    off += cnt[r];
   }
   if (a.xx) {
     const double p = wave_sum(sxx);
-    if (lane == 0) acc[a.nx + a.ny] = p;
+    if (lane == 0) acc[a.nx + a.ny + a.nz] = p;
   }
 }
 
