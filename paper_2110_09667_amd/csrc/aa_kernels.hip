@@ -160,6 +160,11 @@ __global__ __launch_bounds__(kWG) void k_rotate(RotArgs a, Small sm) {
 #define AA_ROT_CH_WIDE 32
 #endif
 constexpr int kRotChWide = AA_ROT_CH_WIDE;
+// Load depth in the 16- and 32-column kernels.
+#ifndef AA_ROT_CH_MID
+#define AA_ROT_CH_MID 8
+#endif
+constexpr int kRotChMid = AA_ROT_CH_MID;
 
 template <int KMAX, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_rotate_gram(RotArgs a, Small sm) {
@@ -170,7 +175,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_rotate_gram(RotArgs a, Small sm)
   givens_coefs(a, sm.cap, s_c, s_s, KMAX);
   __syncthreads();
   v4d acc[GramShape<KMAX>::NBP];
-  rotate_gram_body<KMAX, 64 * WAVES, (KMAX >= 64 ? kRotChWide : kRotCh)>(
+  rotate_gram_body<KMAX, 64 * WAVES, (KMAX >= 64 ? kRotChWide : kRotChMid)>(
       a, s_c, s_s, blockIdx.x, gridDim.x, s_buf, gram_stride(na), acc);
   __syncthreads();  // the staging area becomes the per-wave pair accumulators
   gram_store<KMAX>(acc, s_buf + (threadIdx.x >> 6) * np, na);

@@ -187,16 +187,14 @@ __device__ inline void dots_body(const DotsArgs& a, int64_t t0, int64_t ts, doub
   const int lane = threadIdx.x & 63;
   int nq = a.nx > a.ny ? a.nx : a.ny;
   if (a.nz > nq) nq = a.nz;
+  double sxx = 0.0;  // this lane's share of x^T x
   for_tiles(a.n, t0, ts, [&](int64_t b2, auto full) {
     constexpr bool F = decltype(full)::value;
     double2 xv[kPairs], yv[kPairs], zv[kPairs];
     ld2<F>(xv, a.x, b2, a.n);
     if (a.ny > 0) ld2<F>(yv, a.y, b2, a.n);
     if (a.nz > 0) ld2<F>(zv, a.z, b2, a.n);
-    if (a.xx) {
-      const double p = wave_sum(dot2(xv, xv));
-      if (lane == 0) acc[a.nx + a.ny + a.nz] += p;
-    }
+    if (a.xx) sxx += dot2(xv, xv);
     for (int j0 = 0; j0 < nq; j0 += kGroup) {
       double2 q[kGroup][kPairs];
 #pragma unroll
@@ -249,6 +247,10 @@ __device__ inline void dots_body(const DotsArgs& a, int64_t t0, int64_t ts, doub
       }
     }
   });
+  if (a.xx) {
+    const double p = wave_sum(sxx);
+    if (lane == 0) acc[a.nx + a.ny + a.nz] += p;
+  }
 }
 
 // Register-accumulated block dot products for at most KQ columns and NR
@@ -365,6 +367,7 @@ __device__ inline void update_body(const UpdArgs& a, const double* s_c1, const d
   const int lane = threadIdx.x & 63;
   const int inorm = a.dotcol >= 0 ? 1 : 0;
   const double* c2 = a.c2 ? s_c2 : nullptr;
+  double sdot = 0.0, snrm = 0.0, srhs = 0.0;  // this lane's running sums
   for_tiles(a.n, t0, ts, [&](int64_t b2, auto full) {
     constexpr bool F = decltype(full)::value;
     double2 o[kPairs], dq[kPairs], acc1[kPairs], acc2[kPairs];
@@ -401,21 +404,27 @@ __device__ inline void update_body(const UpdArgs& a, const double* s_c1, const d
       }
     }
     if (a.out) st2<F>(o, a.out, b2, a.n);
-    if (a.dotcol >= 0) {
-      const double p = wave_sum(dot2(dq, o));
-      if (lane == 0) acc[0] += p;
-    }
-    if (a.nrm) {
-      const double p = wave_sum(dot2(o, o));
-      if (lane == 0) acc[inorm] += p;
-    }
+    if (a.dotcol >= 0) sdot += dot2(dq, o);
+    if (a.nrm) snrm += dot2(o, o);
     if (a.rhsv) {
       double2 fv[kPairs];
       ld2<F>(fv, a.rhsv, b2, a.n);
-      const double p = wave_sum(dot2(fv, o));
-      if (lane == 0) acc[inorm + (a.nrm ? 1 : 0)] += p;
+      srhs += dot2(fv, o);
     }
   });
+  // one wave reduction per value, after all of this lane's tiles
+  if (a.dotcol >= 0) {
+    const double p = wave_sum(sdot);
+    if (lane == 0) acc[0] += p;
+  }
+  if (a.nrm) {
+    const double p = wave_sum(snrm);
+    if (lane == 0) acc[inorm] += p;
+  }
+  if (a.rhsv) {
+    const double p = wave_sum(srhs);
+    if (lane == 0) acc[inorm + (a.nrm ? 1 : 0)] += p;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -528,6 +537,11 @@ __device__ inline void givens_coefs(const RotArgs& a, int cap, double* s_c, doub
 // CH is the number of loads a lane keeps in flight: kernels that run few waves
 // per SIMD (wide Gram staging) need a deeper chunk to keep HBM busy.
 constexpr int kRotCh = 8;
+// Load depth of the paired-row sweep of the plain rotation pass.
+#ifndef AA_ROT_CH_PAIR
+#define AA_ROT_CH_PAIR 8
+#endif
+constexpr int kRotChPair = AA_ROT_CH_PAIR;
 
 template <int CH = kRotCh, class Emit>
 __device__ __forceinline__ void rotate_row(const RotArgs& a, int64_t row, bool valid,
@@ -566,28 +580,29 @@ __device__ __forceinline__ void rotate_row(const RotArgs& a, int64_t row, bool v
 
 // The same sweep for two adjacent rows (row even, row + 1 < n) with 16-byte
 // loads and stores.
+template <int CH = kRotCh>
 __device__ __forceinline__ void rotate_pair(const RotArgs& a, int64_t row, const double* s_c,
                                             const double* s_s) {
   const int kk = a.k - 1;
   const double* qrow = a.Q + row;
   f64x2 x = ld2v(reinterpret_cast<const double2*>(qrow));
-  f64x2 nxt[kRotCh];
+  f64x2 nxt[CH];
 #pragma unroll
-  for (int c = 0; c < kRotCh; ++c)
+  for (int c = 0; c < CH; ++c)
     nxt[c] = (1 + c < a.k) ? ld2v(reinterpret_cast<const double2*>(qrow + (int64_t)(1 + c) * a.ldq))
                            : f64x2{0.0, 0.0};
-  for (int j0 = 0; j0 < kk; j0 += kRotCh) {
-    f64x2 cur[kRotCh];
+  for (int j0 = 0; j0 < kk; j0 += CH) {
+    f64x2 cur[CH];
 #pragma unroll
-    for (int c = 0; c < kRotCh; ++c) cur[c] = nxt[c];
+    for (int c = 0; c < CH; ++c) cur[c] = nxt[c];
 #pragma unroll
-    for (int c = 0; c < kRotCh; ++c) {
-      const int jn = j0 + kRotCh + 1 + c;
+    for (int c = 0; c < CH; ++c) {
+      const int jn = j0 + CH + 1 + c;
       nxt[c] = jn < a.k ? ld2v(reinterpret_cast<const double2*>(qrow + (int64_t)jn * a.ldq))
                         : f64x2{0.0, 0.0};
     }
 #pragma unroll
-    for (int c = 0; c < kRotCh; ++c) {
+    for (int c = 0; c < CH; ++c) {
       const int j = j0 + c;
       if (j < kk) {
         const f64x2 y = cur[c];
@@ -611,7 +626,7 @@ __device__ inline void rotate_body(const RotArgs& a, const double* s_c, const do
   for (int64_t tile = t0; tile < ntiles; tile += ts) {
     const int64_t row = 2 * (tile * kWG + threadIdx.x);
     if (row + 1 < a.n)
-      rotate_pair(a, row, s_c, s_s);
+      rotate_pair<kRotChPair>(a, row, s_c, s_s);
     else if (row < a.n)
       rotate_row(a, row, true, s_c, s_s, [](int, double) {});
   }
@@ -968,6 +983,7 @@ __device__ inline void scale_body(const double* in, double* out, int64_t n, doub
 // i == 0: f_prev = g - x, g_prev = g, x_next = g; acc_w[0..1] += ||f||^2.
 __device__ inline void history_body(const HistArgs& a, int64_t t0, int64_t ts, double* acc) {
   const int lane = threadIdx.x & 63;
+  double sff = 0.0;  // this lane's share of ||f||^2 over all its tiles
   for_tiles(a.n, t0, ts, [&](int64_t b2, auto full) {
     constexpr bool F = decltype(full)::value;
     double2 xv[kPairs], gv[kPairs], f[kPairs];
@@ -994,12 +1010,13 @@ __device__ inline void history_body(const HistArgs& a, int64_t t0, int64_t ts, d
       st2<F>(f, a.f_prev, b2, a.n);
       st2<F>(gv, a.g_prev, b2, a.n);
     }
-    const double p = wave_sum(dot2(f, f));
-    if (lane == 0) {
-      acc[0] += p;
-      acc[1] += p;  // first step: x_1 - x_0 = f_0
-    }
+    sff += dot2(f, f);
   });
+  const double p = wave_sum(sff);
+  if (lane == 0) {
+    acc[0] += p;
+    acc[1] += p;  // first step: x_1 - x_0 = f_0
+  }
 }
 
 // Alg. 1: x_{i+1} = g_i - sum_j gamma_j Delta g_{i-m_i+j}; acc_w[0] += ||x_{i+1}-x_i||^2.
@@ -1013,6 +1030,7 @@ __device__ inline void xupdate_coefs(const XupdArgs& a, double* s_g, int* s_slot
 __device__ inline void xupdate_body(const XupdArgs& a, const double* s_g, const int* s_slot,
                                     int64_t t0, int64_t ts, double* acc) {
   const int lane = threadIdx.x & 63;
+  double sdx = 0.0;  // this lane's share of ||x_{i+1} - x_i||^2
   for_tiles(a.n, t0, ts, [&](int64_t b2, auto full) {
     constexpr bool F = decltype(full)::value;
     double2 gv[kPairs], xv[kPairs], sum[kPairs];
@@ -1042,9 +1060,10 @@ __device__ inline void xupdate_body(const XupdArgs& a, const double* s_g, const 
       gv[i] = xn;
     }
     st2<F>(gv, a.x_next, b2, a.n);
-    const double p = wave_sum(d2);
-    if (lane == 0) acc[0] += p;
+    sdx += d2;
   });
+  const double p = wave_sum(sdx);
+  if (lane == 0) acc[0] += p;
 }
 
 }  // namespace aa
