@@ -15,6 +15,15 @@
 // workgroup); the dense tails are the same as in the grid path.
 #include <math.h>
 
+// Row pairs per lane per tile in this translation unit.  One workgroup walks
+// an instance's whole vectors, waiting on every tile's loads in turn, so
+// longer tiles (fewer waits) pay here: four pairs instead of the grid passes'
+// two took the one-instance step from 84 to 77 us (n = 4096, m = 5) and from
+// 654 to 564 us (n = 13824, m = 20).  Only device code sees the value (no
+// host code shares it), so the two translation units may differ.
+#ifndef AA_PAIRS
+#define AA_PAIRS 4
+#endif
 #include "aa_passes.h"
 
 namespace aa {
