@@ -199,8 +199,43 @@ __device__ void wg_qr_add(const BInst& I, int variant, unsigned flags, int k, co
   wg_scale<L>(sm, k, slotk, slotk, I.n);
 }
 
+// Rotation sweep of r plus the strict lower Gram of its staged columns
+// (gram_cols(r): the rotated ones, minus the last with drop_last, then v and
+// f), summed over the workgroup into red[a (a - 1) / 2 + b], b < a.  Up to 8
+// rotated-or-staged columns on the vector units (rotate_gram_small_body: a
+// 16 x 16 MFMA block would spend 256 multiply-adds per row on them), wider
+// windows on the matrix cores (rotate_gram_body).
+template <int KG>
+__device__ void wg_rotate_gram(const RotArgs& r, const double* gc, const double* gs, double* red) {
+  const int na = gram_cols(r), np = na * (na - 1) / 2;
+  if (r.k - 1 + r.naug <= 8) {
+    double acc[32];
+    rotate_gram_small_body<8>(r, gc, gs, 0, 1, acc);
+    const double v = multi_reduce<32>(acc);  // lane l < 32: pair l over the wave
+    const int lane = threadIdx.x & 63;
+    if (lane < np) batch_dyn[(threadIdx.x >> 6) * np + lane] = v;
+  } else {
+    using S = GramShape<KG>;
+    v4d acc[S::NBP];
+    rotate_gram_body<KG>(r, gc, gs, 0, 1, batch_dyn, gram_stride(na), acc);
+    __syncthreads();
+    gram_store<KG>(acc, batch_dyn + (threadIdx.x >> 6) * np, na);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < np; c += kWG) {
+    double s = batch_dyn[c];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) s += batch_dyn[w * np + c];
+    red[c] = s;
+  }
+  __syncthreads();
+}
+
 // QRDelete (Alg. 2): Givens rotations from R, one sweep over Q; ICWY also
-// refreshes T (Gram of the rotated columns on the matrix cores).
+// refreshes T (Gram of the rotated columns).  The QRAdd that follows in the
+// same iteration recomputes the last row of T from its first reduction
+// (Alg. 4) before anything reads it, so the Gram leaves the last rotated
+// column out.
 template <int KB, bool GRAM, class L>
 __device__ void wg_qr_delete(const BInst& I, int variant, int k, L& lds) {
   const Small& sm = I.sm;
@@ -212,22 +247,10 @@ __device__ void wg_qr_delete(const BInst& I, int variant, int k, L& lds) {
   __syncthreads();
   if constexpr (GRAM) {
     if (variant == AA_ICWY) {
-      constexpr int KG = L::KG;
-      using S = GramShape<KG>;
-      const int kk = k - 1, nred = kk * (kk - 1) / 2;
-      v4d acc[S::NBP];
-      rotate_gram_body<KG>(r, lds.gc, lds.gs, 0, 1, batch_dyn, gram_stride(kk), acc);
-      __syncthreads();
-      gram_store<KG>(acc, batch_dyn + (threadIdx.x >> 6) * nred, kk);
-      __syncthreads();
-      for (int c = threadIdx.x; c < nred; c += kWG) {
-        double s = batch_dyn[c];
-#pragma unroll
-        for (int w = 1; w < kWaves; ++w) s += batch_dyn[w * nred + c];
-        lds.red[c] = s;
-      }
-      __syncthreads();
-      run_tail(sm, mk_tail(TAIL_GRAM, kk), lds.red);
+      r.gram = 1;
+      r.drop_last = 1;
+      wg_rotate_gram<L::KG>(r, lds.gc, lds.gs, lds.red);
+      run_tail(sm, mk_tail(TAIL_GRAM, gram_cols(r)), lds.red);
       __syncthreads();
       return;
     }
@@ -317,21 +340,8 @@ __device__ void wg_delete_first_pass(const BInst& I, int variant, unsigned flags
     RotArgs r{I.Q, I.ld, I.n, k, sm.givens, 1, v, f, naug};
     givens_coefs(r, sm.cap, lds.gc, lds.gs, L::KG);
     __syncthreads();
-    constexpr int KG = L::KG;
-    using S = GramShape<KG>;
-    const int kk = k - 1, na = kk + naug, np = na * (na - 1) / 2;
-    v4d acc[S::NBP];
-    rotate_gram_body<KG>(r, lds.gc, lds.gs, 0, 1, batch_dyn, gram_stride(na), acc);
-    __syncthreads();
-    gram_store<KG>(acc, batch_dyn + (threadIdx.x >> 6) * np, na);
-    __syncthreads();
-    for (int c = threadIdx.x; c < np; c += kWG) {
-      double s = batch_dyn[c];
-#pragma unroll
-      for (int w = 1; w < kWaves; ++w) s += batch_dyn[w * np + c];
-      lds.red[c] = s;
-    }
-    __syncthreads();
+    const int kk = k - 1;
+    wg_rotate_gram<L::KG>(r, lds.gc, lds.gs, lds.red);
     if (variant == AA_ICWY) {
       run_tail(sm, mk_tail(TAIL_GRAM, kk), lds.red);
       __syncthreads();
