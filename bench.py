@@ -339,6 +339,45 @@ def poisson1d_to_tolerance(variant, tol=1e-8, cap=300, check_every=1):
             "batch_api_fused_passes_ms": round(1e3 * batch_s["fused"], 3)}
 
 
+def nonlinear3d_to_tolerance(prob, m, variant, tol=1e-8, cap=20000, check_every=10, flags=0):
+    """The 3D nonlinear workload solved from u_0 = 0 to ||f_i|| <= tol ||f_0||
+    (or the cap) with the single-instance entry points, the stop test read
+    every ``check_every`` steps.  Returns iterations, wall seconds (G
+    evaluations included), the final relative residual and whether it
+    converged."""
+    import torch
+    from paper_2110_09667_amd import aa
+    dev = torch.device("cuda:0")
+    f_d = device_rhs(prob)
+    ctx = aa.AAContext(prob.n, m, variant, flags)
+    x = torch.zeros(prob.n, dtype=torch.float64, device=dev)
+    g = torch.empty_like(x)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    it = 0
+    info = None
+    while it < cap:
+        aa.aa_problem_apply(prob.d, prob.s, prob.h, prob.omega, prob.c, f_d, x, g)
+        ctx.step(x, g, x)
+        it += 1
+        if it % check_every == 0 or it == cap:
+            info = ctx.info()
+            if info.status != 0:
+                break
+            if info.iter > 1 and info.res_norm <= tol * info.res0_norm:
+                break
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    info = ctx.info()
+    ctx.close()
+    del f_d, x, g
+    torch.cuda.empty_cache()
+    rel = info.res_norm / info.res0_norm
+    return {"iterations": it, "converged": bool(rel <= tol), "final_rel_residual": rel,
+            "wall_s": round(wall, 3), "ms_per_iter": round(1e3 * wall / max(it, 1), 4),
+            "status": int(info.status)}
+
+
 def one_at_a_time(probs, ms, variant, tol, cap, check_every=10, flags=0):
     """The same instances solved one after another through the single-instance
     entry points (aa_problem_apply + aa_step on one context per instance),
@@ -581,6 +620,11 @@ def main():
     ap.add_argument("--train-iters", type=int, default=50)
     ap.add_argument("--single-sample", type=int, default=64,
                     help="instances run one at a time for the comparison")
+    ap.add_argument("--c2-to-tol", action="store_true",
+                    help="only the 3D nonlinear workload (256^3) solved to 1e-8 per variant and "
+                         "m in {5, 10, 20, 50} (long: several minutes; one JSON line each)")
+    ap.add_argument("--c2-cap", type=int, default=20000,
+                    help="iteration cap of --c2-to-tol")
     ap.add_argument("--poisson-only", action="store_true",
                     help="only the 1D Poisson time-to-tolerance measurement (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -618,6 +662,15 @@ def main():
     if args.poisson_only:
         for v in VARIANTS:
             print(json.dumps({v: poisson1d_to_tolerance(v)}), flush=True)
+        return
+
+    if args.c2_to_tol:
+        prob = Problem3D(args.s)
+        for mm in (5, 10, 20, 50):
+            for v in VARIANTS:
+                r = nonlinear3d_to_tolerance(prob, mm, v, cap=args.c2_cap)
+                print(json.dumps({"workload": f"3D nonlinear {args.s}^3 to 1e-8", "m": mm,
+                                  "variant": v, **r}), flush=True)
         return
 
     prob = Problem3D(args.s)

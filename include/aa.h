@@ -145,7 +145,10 @@ aa_status aa_get_info(aa_ctx *ctx, aa_info *h_info);
 aa_status aa_qr_add(aa_ctx *ctx, const double *d_v);
 
 /* QRDelete (Alg. 2): drop column 0 by Givens rotations; k -> k - 1.
- * ICWY also refreshes T with one reduction.  AA_ESTATE if k == 0. */
+ * ICWY also refreshes every row of T (T_ab = q_a^T q_b, b < a) with one
+ * reduction.  (Inside aa_step, where a QRAdd always follows, the refresh
+ * leaves the newest row to that QRAdd, whose first reduction recomputes it,
+ * Alg. 4; the state after the step is the same.)  AA_ESTATE if k == 0. */
 aa_status aa_qr_delete(aa_ctx *ctx);
 
 /* Solve R gamma = Q^T d_f (Alg. 2, last line); d_gamma receives k doubles
