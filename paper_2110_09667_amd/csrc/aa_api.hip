@@ -62,7 +62,7 @@ namespace {
 constexpr size_t kAlign = 256;
 // Reduction partials: room for kMaxRed values from 4096 workgroups (the
 // largest streaming grid), which also covers the Gram pass below.
-constexpr size_t kPartials = (size_t)kMaxRed * 4096;
+constexpr size_t kPartials = (size_t)kMaxRed * 8192;  // 12.8 MB: the 63-column Gram at 512 workgroups
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 

@@ -381,6 +381,28 @@ hipError_t launch_givens(const Small& sm, int k, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Workgroups of `kernel` (threads, dynamic LDS) that the device holds at once;
+// 0 if unknown.  A grid-stride pass launched with more than that runs its
+// last round on part of the chip (the Gram kernels hold only 2-4 workgroups
+// per compute unit).
+static int resident_workgroups(const void* kernel, int threads, size_t lds) {
+  int dev = 0, cus = 0, per_cu = 0;
+  const bool ok =
+      hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();  // a failed query must not be reported by the launch
+    return 0;
+  }
+  return per_cu * cus;
+}
+
+static int clamp_resident(int grid, const void* kernel, int threads, size_t lds) {
+  const int r = resident_workgroups(kernel, threads, lds);
+  return (r > 0 && grid > r) ? r : grid;
+}
+
 hipError_t launch_rotate(const RotArgs& a, const Small& sm, const Tail& t, int grid,
                          hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
@@ -390,22 +412,41 @@ hipError_t launch_rotate(const RotArgs& a, const Small& sm, const Tail& t, int g
     // The Gram's own column count na sizes the dynamic LDS (fewer columns,
     // more resident workgroups) and picks the 64-column variant.
     const int na = gram_cols(a), w = a.k - 1 + a.naug;
+    // one round of resident workgroups at most (the finalize sums `grid`
+    // partials per value)
+    auto go = [&](const void* kern, int threads, size_t lds, auto launch) {
+      grid = clamp_resident(grid, kern, threads, lds);
+      launch(grid, threads, lds);
+    };
     if (w <= 4) {
-      hipLaunchKernelGGL(k_rotate_gram_small<4>, dim3(grid), dim3(kWG), 0, st, a, sm);
+      go(reinterpret_cast<const void*>(&k_rotate_gram_small<4>), kWG, 0, [&](int g, int th, size_t l) {
+        hipLaunchKernelGGL(k_rotate_gram_small<4>, dim3(g), dim3(th), l, st, a, sm);
+      });
     } else if (w <= kGramSmall) {
-      hipLaunchKernelGGL(k_rotate_gram_small<kGramSmall>, dim3(grid), dim3(kWG), 0, st, a, sm);
+      go(reinterpret_cast<const void*>(&k_rotate_gram_small<kGramSmall>), kWG, 0,
+         [&](int g, int th, size_t l) {
+           hipLaunchKernelGGL(k_rotate_gram_small<kGramSmall>, dim3(g), dim3(th), l, st, a, sm);
+         });
     } else if (w <= 16) {
-      const size_t lds = sizeof(double) * (size_t)gram_lds_doubles(na, kWaves);
-      hipLaunchKernelGGL((k_rotate_gram<16, kWaves>), dim3(grid), dim3(kWG), lds, st, a, sm);
+      go(reinterpret_cast<const void*>(&k_rotate_gram<16, kWaves>), kWG,
+         sizeof(double) * (size_t)gram_lds_doubles(na, kWaves), [&](int g, int th, size_t l) {
+           hipLaunchKernelGGL((k_rotate_gram<16, kWaves>), dim3(g), dim3(th), l, st, a, sm);
+         });
     } else if (w <= 32) {
-      const size_t lds = sizeof(double) * (size_t)gram_lds_doubles(na, kWaves);
-      hipLaunchKernelGGL((k_rotate_gram<32, kWaves>), dim3(grid), dim3(kWG), lds, st, a, sm);
+      go(reinterpret_cast<const void*>(&k_rotate_gram<32, kWaves>), kWG,
+         sizeof(double) * (size_t)gram_lds_doubles(na, kWaves), [&](int g, int th, size_t l) {
+           hipLaunchKernelGGL((k_rotate_gram<32, kWaves>), dim3(g), dim3(th), l, st, a, sm);
+         });
     } else if (w <= 64 && na < kGramSplitMin) {
-      const size_t lds = sizeof(double) * (size_t)gram_lds_doubles(na, 2);
-      hipLaunchKernelGGL((k_rotate_gram<64, 2>), dim3(grid), dim3(128), lds, st, a, sm);
+      go(reinterpret_cast<const void*>(&k_rotate_gram<64, 2>), 128,
+         sizeof(double) * (size_t)gram_lds_doubles(na, 2), [&](int g, int th, size_t l) {
+           hipLaunchKernelGGL((k_rotate_gram<64, 2>), dim3(g), dim3(th), l, st, a, sm);
+         });
     } else if (w <= 64) {  // na >= kGramSplitMin > 32, as the half staging needs
-      const size_t lds = sizeof(double) * (size_t)gram_split_lds_doubles(na);
-      hipLaunchKernelGGL(k_rotate_gram_split, dim3(grid), dim3(kWG), lds, st, a, sm);
+      go(reinterpret_cast<const void*>(&k_rotate_gram_split), kWG,
+         sizeof(double) * (size_t)gram_split_lds_doubles(na), [&](int g, int th, size_t l) {
+           hipLaunchKernelGGL(k_rotate_gram_split, dim3(g), dim3(th), l, st, a, sm);
+         });
     } else {
       return hipErrorInvalidValue;  // at most 64 rotated or staged columns
     }
