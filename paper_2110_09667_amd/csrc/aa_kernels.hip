@@ -12,6 +12,8 @@
 // aa_passes.h (shared with the workgroup-level batched step).
 #include <math.h>
 
+#include <mutex>
+
 #include "aa_passes.h"
 
 namespace aa {
@@ -308,6 +310,47 @@ void set_profile_mid(hipEvent_t e) {
 
 bool profile_mid_used() { return t_prof_mid_used; }
 
+// Workgroups of `kernel` (threads, dynamic LDS) that the device holds at once;
+// 0 if unknown.  A grid-stride pass launched with more workgroups than that
+// (but fewer than twice as many) runs its last round on part of the chip: the
+// Gram kernels hold 2-4 workgroups per compute unit, some dot-product
+// instances 3.  Answers are cached per (device, kernel, threads, LDS).
+static int resident_workgroups(const void* kernel, int threads, size_t lds) {
+  struct Entry { const void* k; int threads; size_t lds; int dev; int res; };
+  static Entry cache[128];
+  static int used = 0;
+  static std::mutex mu;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  {
+    std::lock_guard<std::mutex> g(mu);
+    for (int i = 0; i < used; ++i)
+      if (cache[i].k == kernel && cache[i].threads == threads && cache[i].lds == lds &&
+          cache[i].dev == dev)
+        return cache[i].res;
+  }
+  int cus = 0, per_cu = 0;
+  const bool ok =
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();  // a failed query must not be reported by the launch
+    return 0;
+  }
+  const int res = per_cu * cus;
+  std::lock_guard<std::mutex> g(mu);
+  if (used < 128) cache[used++] = Entry{kernel, threads, lds, dev, res};
+  return res;
+}
+
+static int clamp_resident(int grid, const void* kernel, int threads, size_t lds) {
+  const int r = resident_workgroups(kernel, threads, lds);
+  return (r > 0 && grid > r) ? r : grid;
+}
+
 static hipError_t launch_finalize(const Small& sm, const Tail& t, int nred, int grid,
                                   hipStream_t st) {
   hipError_t e = hipGetLastError();
@@ -326,37 +369,66 @@ hipError_t launch_dots(const DotsArgs& a, const Small& sm, const Tail& t, int gr
   (void)hipGetLastError();  // drop a stale error left by an earlier call
   // every vector the counts name must exist
   if (!a.x || (a.ny > 0 && !a.y) || (a.nz > 0 && !a.z)) return hipErrorInvalidValue;
+  // one round of resident workgroups at most; the finalize sums `grid` partials
+  auto clamp_launch = [&](const void* kern, auto launch) {
+    const int g = clamp_resident(grid, kern, kWG, 0);
+    launch(g);
+    return g;
+  };
   int nq = a.nx > a.ny ? a.nx : a.ny;
   if (a.nz > nq) nq = a.nz;
   const int nr = a.nz > 0 ? 3 : (a.ny > 0 ? 2 : 1);  // right-hand sides
   if (AA_DOTS_REG && nr == 1 && nq <= 8)
-    hipLaunchKernelGGL((k_dots_reg<8, 1>), dim3(grid), dim3(kWG), 0, st, a, sm);
+    grid = clamp_launch(reinterpret_cast<const void*>(&k_dots_reg<8, 1>), [&](int g) {
+      hipLaunchKernelGGL((k_dots_reg<8, 1>), dim3(g), dim3(kWG), 0, st, a, sm);
+    });
   else if (AA_DOTS_REG && nr == 1 && nq <= 16)
-    hipLaunchKernelGGL((k_dots_reg<16, 1>), dim3(grid), dim3(kWG), 0, st, a, sm);
+    grid = clamp_launch(reinterpret_cast<const void*>(&k_dots_reg<16, 1>), [&](int g) {
+      hipLaunchKernelGGL((k_dots_reg<16, 1>), dim3(g), dim3(kWG), 0, st, a, sm);
+    });
   else if (AA_DOTS_REG && nr == 1 && nq <= 32)
-    hipLaunchKernelGGL((k_dots_reg<32, 1>), dim3(grid), dim3(kWG), 0, st, a, sm);
+    grid = clamp_launch(reinterpret_cast<const void*>(&k_dots_reg<32, 1>), [&](int g) {
+      hipLaunchKernelGGL((k_dots_reg<32, 1>), dim3(g), dim3(kWG), 0, st, a, sm);
+    });
   else if (AA_DOTS_REG && nr == 1 && nq <= 64)
-    hipLaunchKernelGGL((k_dots_reg<64, 1>), dim3(grid), dim3(kWG), 0, st, a, sm);
+    grid = clamp_launch(reinterpret_cast<const void*>(&k_dots_reg<64, 1>), [&](int g) {
+      hipLaunchKernelGGL((k_dots_reg<64, 1>), dim3(g), dim3(kWG), 0, st, a, sm);
+    });
   else if (AA_DOTS_REG && nr == 2 && nq <= 8)
-    hipLaunchKernelGGL((k_dots_reg<8, 2>), dim3(grid), dim3(kWG), 0, st, a, sm);
+    grid = clamp_launch(reinterpret_cast<const void*>(&k_dots_reg<8, 2>), [&](int g) {
+      hipLaunchKernelGGL((k_dots_reg<8, 2>), dim3(g), dim3(kWG), 0, st, a, sm);
+    });
   else if (AA_DOTS_REG && nr == 2 && nq <= 16)
-    hipLaunchKernelGGL((k_dots_reg<16, 2>), dim3(grid), dim3(kWG), 0, st, a, sm);
+    grid = clamp_launch(reinterpret_cast<const void*>(&k_dots_reg<16, 2>), [&](int g) {
+      hipLaunchKernelGGL((k_dots_reg<16, 2>), dim3(g), dim3(kWG), 0, st, a, sm);
+    });
   else if (AA_DOTS_REG && nr == 2 && nq <= 32)
-    hipLaunchKernelGGL((k_dots_reg<32, 2>), dim3(grid), dim3(kWG), 0, st, a, sm);
+    grid = clamp_launch(reinterpret_cast<const void*>(&k_dots_reg<32, 2>), [&](int g) {
+      hipLaunchKernelGGL((k_dots_reg<32, 2>), dim3(g), dim3(kWG), 0, st, a, sm);
+    });
   else if (AA_DOTS_REG3 && nr == 3 && nq <= 8)
-    hipLaunchKernelGGL((k_dots_reg<8, 3>), dim3(grid), dim3(kWG), 0, st, a, sm);
+    grid = clamp_launch(reinterpret_cast<const void*>(&k_dots_reg<8, 3>), [&](int g) {
+      hipLaunchKernelGGL((k_dots_reg<8, 3>), dim3(g), dim3(kWG), 0, st, a, sm);
+    });
   else if (AA_DOTS_REG3 && nr == 3 && nq <= 16)
-    hipLaunchKernelGGL((k_dots_reg<16, 3>), dim3(grid), dim3(kWG), 0, st, a, sm);
+    grid = clamp_launch(reinterpret_cast<const void*>(&k_dots_reg<16, 3>), [&](int g) {
+      hipLaunchKernelGGL((k_dots_reg<16, 3>), dim3(g), dim3(kWG), 0, st, a, sm);
+    });
   else if (AA_DOTS_REG3 && nr == 3 && nq <= 32)
-    hipLaunchKernelGGL((k_dots_reg<32, 3>), dim3(grid), dim3(kWG), 0, st, a, sm);
+    grid = clamp_launch(reinterpret_cast<const void*>(&k_dots_reg<32, 3>), [&](int g) {
+      hipLaunchKernelGGL((k_dots_reg<32, 3>), dim3(g), dim3(kWG), 0, st, a, sm);
+    });
   else
-    hipLaunchKernelGGL(k_dots, dim3(grid), dim3(kWG), 0, st, a, sm);
+    grid = clamp_launch(reinterpret_cast<const void*>(&k_dots), [&](int g) {
+      hipLaunchKernelGGL(k_dots, dim3(g), dim3(kWG), 0, st, a, sm);
+    });
   return launch_finalize(sm, t, a.nx + a.ny + a.nz + (a.xx ? 1 : 0), grid, st);
 }
 
 hipError_t launch_update(const UpdArgs& a, const Small& sm, const Tail& t, int grid,
                          hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
+  grid = clamp_resident(grid, reinterpret_cast<const void*>(&k_update), kWG, 0);
   hipLaunchKernelGGL(k_update, dim3(grid), dim3(kWG), 0, st, a, sm);
   return launch_finalize(sm, t, update_nred(a), grid, st);
 }
@@ -364,14 +436,23 @@ hipError_t launch_update(const UpdArgs& a, const Small& sm, const Tail& t, int g
 hipError_t launch_cgs2b(const Cgs2bArgs& a, const Small& sm, const Tail& t, int grid,
                         hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
-  if (a.k <= 8)
-    hipLaunchKernelGGL(k_cgs2b<8>, dim3(grid), dim3(kWG), 0, st, a, sm);
-  else if (a.k <= 16)
-    hipLaunchKernelGGL(k_cgs2b<16>, dim3(grid), dim3(kWG), 0, st, a, sm);
-  else if (a.k <= 32)
-    hipLaunchKernelGGL(k_cgs2b<32>, dim3(grid), dim3(kWG), 0, st, a, sm);
-  else
-    hipLaunchKernelGGL(k_cgs2b<64>, dim3(grid), dim3(kWG), 0, st, a, sm);
+  auto go = [&](const void* kern, auto launch) {
+    grid = clamp_resident(grid, kern, kWG, 0);
+    launch();
+  };
+  if (a.k <= 8) {
+    go(reinterpret_cast<const void*>(&k_cgs2b<8>),
+       [&] { hipLaunchKernelGGL(k_cgs2b<8>, dim3(grid), dim3(kWG), 0, st, a, sm); });
+  } else if (a.k <= 16) {
+    go(reinterpret_cast<const void*>(&k_cgs2b<16>),
+       [&] { hipLaunchKernelGGL(k_cgs2b<16>, dim3(grid), dim3(kWG), 0, st, a, sm); });
+  } else if (a.k <= 32) {
+    go(reinterpret_cast<const void*>(&k_cgs2b<32>),
+       [&] { hipLaunchKernelGGL(k_cgs2b<32>, dim3(grid), dim3(kWG), 0, st, a, sm); });
+  } else {
+    go(reinterpret_cast<const void*>(&k_cgs2b<64>),
+       [&] { hipLaunchKernelGGL(k_cgs2b<64>, dim3(grid), dim3(kWG), 0, st, a, sm); });
+  }
   return launch_finalize(sm, t, a.k, grid, st);
 }
 
@@ -379,28 +460,6 @@ hipError_t launch_givens(const Small& sm, int k, hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
   hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, sm, k);
   return hipGetLastError();
-}
-
-// Workgroups of `kernel` (threads, dynamic LDS) that the device holds at once;
-// 0 if unknown.  A grid-stride pass launched with more than that runs its
-// last round on part of the chip (the Gram kernels hold only 2-4 workgroups
-// per compute unit).
-static int resident_workgroups(const void* kernel, int threads, size_t lds) {
-  int dev = 0, cus = 0, per_cu = 0;
-  const bool ok =
-      hipGetDevice(&dev) == hipSuccess &&
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) == hipSuccess;
-  if (!ok) {
-    (void)hipGetLastError();  // a failed query must not be reported by the launch
-    return 0;
-  }
-  return per_cu * cus;
-}
-
-static int clamp_resident(int grid, const void* kernel, int threads, size_t lds) {
-  const int r = resident_workgroups(kernel, threads, lds);
-  return (r > 0 && grid > r) ? r : grid;
 }
 
 hipError_t launch_rotate(const RotArgs& a, const Small& sm, const Tail& t, int grid,
@@ -469,6 +528,7 @@ hipError_t launch_scale(const ScaleArgs& a, const Small& sm, hipStream_t st) {
 hipError_t launch_history(const HistArgs& a, const Small& sm, const Tail& t, int grid,
                           hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
+  grid = clamp_resident(grid, reinterpret_cast<const void*>(&k_history), kWG, 0);
   hipLaunchKernelGGL(k_history, dim3(grid), dim3(kWG), 0, st, a, sm);
   return launch_finalize(sm, t, a.first ? 2 : 1, grid, st);
 }
@@ -476,6 +536,7 @@ hipError_t launch_history(const HistArgs& a, const Small& sm, const Tail& t, int
 hipError_t launch_xupdate(const XupdArgs& a, const Small& sm, const Tail& t, int grid,
                           hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
+  grid = clamp_resident(grid, reinterpret_cast<const void*>(&k_xupdate), kWG, 0);
   hipLaunchKernelGGL(k_xupdate, dim3(grid), dim3(kWG), 0, st, a, sm);
   return launch_finalize(sm, t, 1, grid, st);
 }
