@@ -149,8 +149,12 @@ __device__ void wg_qr_add(const BInst& I, int variant, unsigned flags, int k, co
       dots(d, ts);
       for (int j = threadIdx.x; j < KB; j += kWG) lds.cs[j] = (j < k) ? sm.coef0[j] : 0.0;
       Cgs2bArgs b{I.Q, I.ld, I.n, v, k, sm.coef0};
-      wg_pass(sm, mk_tail(TAIL_CGS2_Z, k), k, lds,
-              [&](double* acc) { cgs2b_stream_body(b, lds.cs, 0, 1, acc); });
+      wg_pass(sm, mk_tail(TAIL_CGS2_Z, k), k, lds, [&](double* acc) {
+        if constexpr (KB <= 8)
+          cgs2b_reg_body<8>(b, lds.cs, 0, 1, acc);
+        else
+          cgs2b_stream_body(b, lds.cs, 0, 1, acc);
+      });
       UpdArgs uc = u;
       uc.v = v; uc.out = slotk; uc.j0 = 0; uc.nc = k; uc.c1 = sm.coef0; uc.c2 = sm.coef1;
       uc.nrm = 1;

@@ -455,6 +455,36 @@ __device__ inline void cgs2b_body(const Cgs2bArgs& a, const double* s_s, int64_t
   }
 }
 
+// The same pass with per-lane running sums (workgroup-level step, at most
+// KMAX columns): per row the same y = v - Q s, then sum_j += q_j y over all of
+// the lane's rows, and one KMAX-wide butterfly per wave at the end instead of
+// one per tile.
+template <int KMAX>
+__device__ inline void cgs2b_reg_body(const Cgs2bArgs& a, const double* s_s, int64_t t0,
+                                      int64_t ts, double* acc) {
+  const int lane = threadIdx.x & 63;
+  const int64_t ntiles = (a.n + kWG - 1) / kWG;
+  double sum[KMAX];
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) sum[j] = 0.0;
+  for (int64_t tile = t0; tile < ntiles; tile += ts) {
+    const int64_t row = tile * kWG + threadIdx.x;
+    const bool valid = row < a.n;
+    double q[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j)
+      q[j] = (j < a.k && valid) ? a.Q[(int64_t)j * a.ldq + row] : 0.0;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) s = fma(q[j], s_s[j], s);
+    const double y = (valid ? a.v[row] : 0.0) - s;
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) sum[j] = fma(q[j], y, sum[j]);
+  }
+  const double r = multi_reduce<KMAX>(sum);
+  if (lane < KMAX && lane < a.k) acc[lane] += r;
+}
+
 // The same pass without a k-wide register array (workgroup-level step): per
 // 256-row tile, one sweep forms y = v - Q s, a second sweep over the same tile
 // (cache-resident, just read) forms Q^T y in groups of kGroup columns.
