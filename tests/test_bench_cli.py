@@ -1,0 +1,26 @@
+"""bench.py's command-line contract on the host (no GPU needed): it runs on
+one GPU only and says so for any other count, and it documents its modes."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def run(*args):
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args],
+                          capture_output=True, text=True, timeout=300, cwd=ROOT)
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = run("--gpus", "2")
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_help_lists_the_measurement_modes():
+    r = run("--help")
+    assert r.returncode == 0
+    for flag in ("--steps", "--warmup", "--gpus", "--c2-to-tol", "--poisson-only",
+                 "--batch-cap", "--copy-calibration"):
+        assert flag in r.stdout, flag
