@@ -620,6 +620,9 @@ def main():
     ap.add_argument("--train-iters", type=int, default=50)
     ap.add_argument("--single-sample", type=int, default=64,
                     help="instances run one at a time for the comparison")
+    ap.add_argument("--qr-micro-only", action="store_true",
+                    help="only the QRAdd / QRDelete microbenchmark at n = 2^26, k = 1 .. 64 "
+                         "(one JSON line per variant; for kernel traces)")
     ap.add_argument("--c2-to-tol", action="store_true",
                     help="only the 3D nonlinear workload (256^3) solved to 1e-8 per variant and "
                          "m in {5, 10, 20, 50} (long: several minutes; one JSON line each)")
@@ -662,6 +665,14 @@ def main():
     if args.poisson_only:
         for v in VARIANTS:
             print(json.dumps({v: poisson1d_to_tolerance(v)}), flush=True)
+        return
+
+    if args.qr_micro_only:
+        for v in VARIANTS:
+            ks = [min(k, 63) if v == "icwy" else k for k in (1, 2, 4, 8, 16, 32, 64)]
+            r = qr_micro(1 << 26, ks, v)
+            print(json.dumps({"variant": v, "n": 1 << 26,
+                              **{f"k={k}": d for k, d in r.items()}}), flush=True)
         return
 
     if args.c2_to_tol:

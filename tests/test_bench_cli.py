@@ -22,5 +22,5 @@ def test_help_lists_the_measurement_modes():
     r = run("--help")
     assert r.returncode == 0
     for flag in ("--steps", "--warmup", "--gpus", "--c2-to-tol", "--poisson-only",
-                 "--batch-cap", "--copy-calibration"):
+                 "--batch-cap", "--copy-calibration", "--qr-micro-only"):
         assert flag in r.stdout, flag
