@@ -215,7 +215,9 @@ aa_status aa_profile_reset(aa_ctx *ctx);
 
 /* Upper bounds on the workgroups of the streaming passes and of the ICWY
  * Gram pass (defaults 1024 and 1024; each in [1, 4096]; the Gram pass also
- * keeps (workgroups) x (k-1)(k-2)/2 within its partials buffer). */
+ * keeps (workgroups) x (k-1)(k-2)/2 within its partials buffer).  A pass is
+ * further limited to the workgroups of its kernel that the device holds at
+ * once (one round), as the occupancy query reports. */
 aa_status aa_set_grid(aa_ctx *ctx, int stream_max, int gram_max);
 
 /* Largest n for which aa_step runs the whole iteration in one workgroup (one
