@@ -104,7 +104,8 @@ typedef struct {
 } aa_info;
 
 /* Bytes of device workspace for a window of m columns over vectors of
- * length n (1 <= m <= AA_MAX_COLS, n >= 1). */
+ * length n (n >= 1; 1 <= m <= 64, or m = AA_MAX_COLS = 65 with AA_QR_ONLY
+ * and a variant other than ICWY).  AA_EINVAL otherwise. */
 aa_status aa_workspace_size(int64_t n, int m, int variant, unsigned flags,
                             size_t *bytes);
 
@@ -152,7 +153,8 @@ aa_status aa_qr_add(aa_ctx *ctx, const double *d_v);
 aa_status aa_qr_delete(aa_ctx *ctx);
 
 /* Solve R gamma = Q^T d_f (Alg. 2, last line); d_gamma receives k doubles
- * (device).  AA_ESTATE if k == 0. */
+ * (device).  AA_ESTATE if k == 0; AA_EINVAL if k > 64 (the solve is for
+ * windows of at most 64 columns). */
 aa_status aa_qr_solve(aa_ctx *ctx, const double *d_f, double *d_gamma);
 
 /* Copy R and T (k x k, column-major, leading dimension k) to host buffers

@@ -536,6 +536,9 @@ extern "C" {
 aa_status aa_workspace_size(int64_t n, int m, int variant, unsigned flags, size_t* bytes) {
   if (!bytes || n < 1 || m < 1 || m > AA_MAX_COLS || !valid_variant(variant)) return AA_EINVAL;
   if (variant == AA_ICWY && m > 64) return AA_EINVAL;
+  // The least-squares solve (one wave, one lane per row of R) reaches 64
+  // columns: the 65th column exists only for the QR update on its own.
+  if (m > 64 && !(flags & AA_QR_ONLY)) return AA_EINVAL;
   *bytes = make_layout(n, m, flags).total;
   return AA_OK;
 }
@@ -760,6 +763,7 @@ aa_status aa_qr_delete(aa_ctx* c) {
 aa_status aa_qr_solve(aa_ctx* c, const double* f, double* gamma) {
   if (!c || !f || !gamma) return AA_EINVAL;
   if (c->k == 0) return AA_ESTATE;
+  if (c->k > 64) return AA_EINVAL;  // the back substitution runs on one 64-lane wave
   aa_status s = rhs_impl(c, f);
   if (s != AA_OK) return s;
   return hip_ok(launch_copy(gamma, c->sm.gamma, c->k, c->stream));

@@ -48,3 +48,23 @@ def gpu_aa_run(prob, m, variant, iters, flags=0, x0=None, record=True, fused=Non
 def rel(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def rel_inf(a, b):
+    """Element-wise comparison as one number: max |a - b| / max |b|."""
+    mb = np.max(np.abs(b))
+    return np.max(np.abs(a - b)) / (mb if mb > 0 else 1.0)
+
+
+def oracle_trajectory(O, prob, m, variant, iters, flags=0):
+    """The oracle's iterates x_0..x_{iters+1} and, per step, kappa_2(R) of the
+    factorization the step solved with (1 before the first QR exists)."""
+    st = O.AA(prob.n, m, variant, flags)
+    x = np.zeros(prob.n)
+    xs, kappas = [x.copy()], [1.0]
+    for _ in range(iters + 1):
+        g = O.G_stencil(prob, x)
+        x = st.step(x, g)
+        xs.append(x.copy())
+        kappas.append(np.linalg.cond(st.Rk()) if st.k > 0 else 1.0)
+    return xs, kappas, st

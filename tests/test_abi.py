@@ -53,6 +53,13 @@ def test_workspace_size_and_argument_errors(L):
     assert L.aa_workspace_size(10, 0, aa.MGS, 0, C.byref(b)) == -1
     assert L.aa_workspace_size(10, 66, aa.MGS, 0, C.byref(b)) == -1
     assert L.aa_workspace_size(10, 65, aa.ICWY, 0, C.byref(b)) == -1
+    assert L.aa_workspace_size(10, 65, aa.ICWY, aa.QR_ONLY, C.byref(b)) == -1
+    # a 65th column only for the QR update on its own: the LSP solve and
+    # aa_step reach 64 columns
+    for v in (aa.MGS, aa.CGS2, aa.DCGS2):
+        assert L.aa_workspace_size(10, 65, v, 0, C.byref(b)) == -1
+        assert L.aa_workspace_size(10, 65, v, aa.QR_ONLY, C.byref(b)) == 0
+        assert L.aa_workspace_size(10, 64, v, 0, C.byref(b)) == 0
     assert L.aa_workspace_size(10, 5, 7, 0, C.byref(b)) == -1
     assert L.aa_workspace_size(10, 5, aa.MGS, 0, None) == -1
     ctx = C.c_void_p()

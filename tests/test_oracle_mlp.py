@@ -122,3 +122,52 @@ def test_decode_masks_and_sigmoid():
     dg, beta = mlp.decode(out, np.array([3, 20]))
     assert np.all(dg[0, :3] == 1.0) and np.all(dg[0, 3:] == 0.0) and np.all(dg[1] == 1.0)
     assert abs(beta[0] - 1 / (1 + np.exp(-4.0))) < 1e-15 and beta[1] == 0.5
+
+
+def test_gelu_fixed_values_and_odd_part():
+    """GELU(z) = z * Phi(z), Phi the standard normal CDF (erf form, no tanh
+    approximation).  Phi at 0.5, 1, 2 are textbook table values; Phi is also
+    recomputed here by integrating the normal density (an independent route);
+    and Phi(z) + Phi(-z) = 1 gives GELU(z) - GELU(-z) = z."""
+    from scipy.integrate import quad
+    table = {0.5: 0.6914624612740131, 1.0: 0.8413447460685429, 2.0: 0.9772498680518208}
+    for z, phi in table.items():
+        assert abs(mlp.gelu(np.array([z]))[0] - z * phi) <= 1e-15 * z
+        dens = quad(lambda t: np.exp(-0.5 * t * t) / np.sqrt(2 * np.pi), -np.inf, z,
+                    epsabs=1e-15, epsrel=1e-14)[0]
+        assert abs(dens - phi) <= 1e-13
+    # the tanh approximation is off by ~1.5e-4 at z = 1: a 1e-12 pin rejects it
+    z = np.linspace(-6.0, 6.0, 241)
+    assert np.max(np.abs(mlp.gelu(z) - mlp.gelu(-z) - z)) <= 1e-14
+    assert mlp.gelu(np.array([0.0]))[0] == 0.0
+    # tails: GELU(z) -> z for large z, -> 0 for very negative z
+    assert abs(mlp.gelu(np.array([10.0]))[0] - 10.0) <= 1e-15 * 10
+    assert abs(mlp.gelu(np.array([-10.0]))[0]) <= 1e-20
+
+
+def test_adam_first_two_steps_closed_form():
+    """Adam (Kingma and Ba, Alg. 1): with bias correction the first step moves
+    every weight by -lr g / (|g| + eps), whatever beta1 and beta2 are; the
+    second step's moments are worked out by hand below, which tells a swap of
+    beta1 and beta2 or a missing bias correction from the right update."""
+    lr, b1, b2, eps = 0.01, 0.9, 0.999, 1e-8
+    g1 = np.array([[0.5, -2.0], [1e-3, 0.0]])
+    g2 = np.array([[-1.5, 4.0], [2e-3, 3.0]])
+    W = np.array([[1.0, 2.0], [3.0, 4.0]])
+    b = np.array([0.25, -0.25])
+    gb1, gb2 = np.array([0.1, -0.2]), np.array([0.3, 0.05])
+    params = [(W.copy(), b.copy())]
+    # per layer: (first, second) moments of W, then of b
+    state = [((np.zeros_like(W), np.zeros_like(W)), (np.zeros_like(b), np.zeros_like(b)))]
+    params = mlp.adam(params, [(g1, gb1)], [state[0]], lr, 1, b1, b2, eps)
+    W1 = W - lr * g1 / (np.abs(g1) + eps)
+    bb1 = b - lr * gb1 / (np.abs(gb1) + eps)
+    assert np.allclose(params[0][0], W1, rtol=0, atol=1e-15)
+    assert np.allclose(params[0][1], bb1, rtol=0, atol=1e-15)
+    params = mlp.adam(params, [(g2, gb2)], [state[0]], lr, 2, b1, b2, eps)
+    # moments after two steps: m = 0.09 g1 + 0.1 g2, v = 0.000999 g1^2 + 0.001 g2^2;
+    # bias corrections 1 - 0.9^2 = 0.19 and 1 - 0.999^2 = 0.001999
+    for P0, ga, gb_, P in ((W1, g1, g2, params[0][0]), (bb1, gb1, gb2, params[0][1])):
+        mh = (0.09 * ga + 0.1 * gb_) / 0.19
+        vh = (0.000999 * ga * ga + 0.001 * gb_ * gb_) / 0.001999
+        assert np.allclose(P, P0 - lr * mh / (np.sqrt(vh) + eps), rtol=0, atol=1e-14)
