@@ -157,6 +157,22 @@ aa_status aa_qr_delete(aa_ctx *ctx);
  * windows of at most 64 columns). */
 aa_status aa_qr_solve(aa_ctx *ctx, const double *d_f, double *d_gamma);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc) and hold no
+ * context: the same solve as aa_qr_solve (R gamma = Q^T f, the same kernels)
+ * on a caller's factorization.  d_Q: k columns of length n, leading dimension
+ * ldq >= n (device); d_R: k x k upper triangular, column-major, leading
+ * dimension ldr >= k, nonsingular (device); d_f: n doubles (device); d_gamma:
+ * k doubles out (device).  1 <= k <= 64, else AA_EINVAL.  Asynchronous on
+ * `stream`.  Allocates nothing: the reduction partials live in a fixed
+ * 513 KiB device array that every GPU the library runs on keeps until the
+ * process ends, shared by all calls on that GPU -- calls that overlap on one
+ * GPU (other streams, other host threads) race and must be serialized by the
+ * caller. */
+aa_status aa_qr_solve_noalloc(const double *d_Q, int64_t ldq, int64_t n, int k,
+                              const double *d_R, int ldr, const double *d_f,
+                              double *d_gamma, void *stream);
+
 /* Copy R and T (k x k, column-major, leading dimension k) to host buffers
  * (either may be NULL) and report k.  Waits for the stream. */
 aa_status aa_get_qr(aa_ctx *ctx, double *h_R, double *h_T, int *k);

@@ -36,7 +36,7 @@ SYMBOLS = [
     "aa_mlp_workspace_size", "aa_mlp_init", "aa_mlp_reseed", "aa_mlp_set_params",
     "aa_mlp_get_params", "aa_mlp_get_grads", "aa_mlp_forward", "aa_mlp_backward",
     "aa_mlp_adam", "aa_mlp_destroy", "aa_batch_run_learned", "aa_batch_train",
-    "aa_batch_read_learning",
+    "aa_batch_read_learning", "aa_qr_solve_noalloc",
 ]
 
 BATCH_LEARNED = 1 << 9
@@ -98,6 +98,7 @@ def lib():
         "aa_qr_add": [P, P],
         "aa_qr_delete": [P],
         "aa_qr_solve": [P, P, P],
+        "aa_qr_solve_noalloc": [P, I64, I64, I, P, I, P, P, P],
         "aa_get_qr": [P, P, P, C.POINTER(C.c_int)],
         "aa_qr_basis": [P, C.POINTER(P), C.POINTER(I64)],
         "aa_qr_load": [P, I, P, I64, P, P],
@@ -198,6 +199,11 @@ def aa_qr_delete(ctx):
 
 def aa_qr_solve(ctx, f, gamma):
     _check(lib().aa_qr_solve(ctx, _ptr(f), _ptr(gamma)), "aa_qr_solve")
+
+
+def aa_qr_solve_noalloc(Q, ldq, n, k, R, ldr, f, gamma, stream=None):
+    _check(lib().aa_qr_solve_noalloc(_ptr(Q), ldq, n, k, _ptr(R), ldr, _ptr(f), _ptr(gamma),
+                                     _stream(stream)), "aa_qr_solve_noalloc")
 
 
 def aa_get_qr(ctx, cap: int):
