@@ -23,9 +23,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "aa_oracle.c")
 
-MGS, CGS2, DCGS2, ICWY = 0, 1, 2, 3
-VARIANTS = {"mgs": MGS, "cgs2": CGS2, "dcgs2": DCGS2, "icwy": ICWY}
+MGS, CGS2, DCGS2, ICWY, DCGS2_LAG = 0, 1, 2, 3, 4
+VARIANTS = {"mgs": MGS, "cgs2": CGS2, "dcgs2": DCGS2, "icwy": ICWY, "dcgs2_lag": DCGS2_LAG}
 DCGS2_LITERAL = 1 << 1
+ICWY_T_TRANSFORM = 1 << 2
 DCGS2_GUARD_GE3 = 1 << 4
 OK, EINVAL, EBREAKDOWN, ESTATE = 0, -1, -3, -4
 
@@ -52,7 +53,8 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.or_qr_add.argtypes = [C.POINTER(_QR), C.c_int, C.c_uint, P]
-        L.or_qr_delete.argtypes = [C.POINTER(_QR), C.c_int]
+        L.or_qr_delete.argtypes = [C.POINTER(_QR), C.c_int, C.c_uint]
+        L.or_qr_flush.argtypes = [C.POINTER(_QR), C.c_int]
         L.or_qr_rhs.argtypes = [C.POINTER(_QR), P, P]
         L.or_qr_rhs.restype = None
         L.or_backsolve.argtypes = [C.c_int, C.c_int, P, P, P]
@@ -123,7 +125,12 @@ class QR:
         return lib().or_qr_add(C.byref(self.s), self.variant, self.flags, _ptr(v))
 
     def delete(self) -> int:
-        return lib().or_qr_delete(C.byref(self.s), self.variant)
+        return lib().or_qr_delete(C.byref(self.s), self.variant, self.flags)
+
+    def flush(self) -> int:
+        """The lagged DCGS-2's final reorthogonalization and normalization of
+        the newest column (one reduction); other variants: EINVAL."""
+        return lib().or_qr_flush(C.byref(self.s), self.variant)
 
     def rhs(self, f) -> np.ndarray:
         f = np.ascontiguousarray(f, dtype=np.float64)

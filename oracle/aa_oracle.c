@@ -30,11 +30,16 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { OR_MGS = 0, OR_CGS2 = 1, OR_DCGS2 = 2, OR_ICWY = 3 };
+/* OR_DCGS2_LAG: the delayed CGS-2 with the normalization lagged as well
+ * (Sec. 3.4 describes it in words, after Swirydowicz et al. and Bielich et
+ * al.; the paper does not use it in AA). */
+enum { OR_MGS = 0, OR_CGS2 = 1, OR_DCGS2 = 2, OR_ICWY = 3, OR_DCGS2_LAG = 4 };
 
 /* Readings of passages the paper leaves open (listed in the design notes). */
 enum {
   OR_DCGS2_LITERAL = 1u << 1, /* Alg. 6: add s itself (not R_kk*s) to R      */
+  OR_ICWY_T_TRANSFORM = 1u << 2, /* ICWY: T after QRDelete by rotating the
+                                    old Gram matrix, no reduction (Sec. 3.2) */
   OR_DCGS2_GUARD_GE3 = 1u << 4 /* Alg. 6: reorthogonalize when m_i >= 3      */
 };
 
@@ -190,6 +195,116 @@ static int qr_add_dcgs2(or_qr *s, double *v, unsigned flags) {
   return normalize_into(s, v);
 }
 
+/* DCGS-2 with the normalization lagged (Sec. 3.4, the stable form the paper
+ * describes but does not run in AA: the correction matrix I - L - L^T split
+ * into I - L, applied when a column is added, and L^T, applied one add
+ * later, with the new column's normalization lagged too).  Invariant: columns
+ * 0..k-2 are final; column k-1 (the newest) has been orthogonalized once and
+ * scaled by a norm obtained from Pythagoras, not from a reduction over it.
+ *
+ * Adding v (k >= 1 columns present, p = k-1 the newest), ONE reduction:
+ *   s = Q_{0:p-1}^T q_p,  z = Q_{0:p-1}^T v,
+ *   alpha = q_p^T q_p,    beta = q_p^T v,    nu = v^T v.
+ * Delayed reorthogonalization and normalization of q_p:
+ *   rho = sqrt(alpha - s^T s),  q_p <- (q_p - Q_{0:p-1} s) / rho,
+ *   and column p of R follows so that Q R = F keeps holding:
+ *   R_{0:p-1,p} += R_pp s,  R_pp <- rho R_pp.
+ * Projection of v on the updated basis (once; its reorthogonalization waits
+ * for the next add):  R_{0:p-1,k} = z,  R_pk = (beta - s^T z) / rho,
+ *   w = v - Q_{0:p-1} z - q_p R_pk,
+ *   R_kk = sqrt(nu - ||R_{0:p,k}||^2)   (Pythagoras: no reduction over w),
+ *   q_k = w / R_kk.
+ * With k = 0 the column is normalized by its explicit norm (one reduction).
+ * A non-positive alpha - s^T s or nu - ||R_{0:p,k}||^2 (cancellation when v
+ * is nearly in the span of Q) is a breakdown. */
+static int qr_add_dcgs2_lag(or_qr *s, double *v) {
+  int k = s->k;
+  if (k == 0) return normalize_into(s, v);
+  int p = k - 1;
+  int64_t n = s->n;
+  double *qp = QCOL(s, p);
+  double *sc = (double *)calloc((size_t)k, sizeof(double));
+  double *zc = (double *)calloc((size_t)k, sizeof(double));
+  for (int j = 0; j < p; ++j) {
+    sc[j] = dot(n, QCOL(s, j), qp);
+    zc[j] = dot(n, QCOL(s, j), v);
+  }
+  double alpha = dot(n, qp, qp), beta = dot(n, qp, v), nu = dot(n, v, v);
+  s->syncs_add += 1; /* all five in one reduction */
+  double ss = 0.0, sz = 0.0;
+  for (int j = 0; j < p; ++j) {
+    ss += sc[j] * sc[j];
+    sz += sc[j] * zc[j];
+  }
+  double rho2 = alpha - ss;
+  int st = OR_OK;
+  if (!(rho2 > 0.0) || !isfinite(rho2)) {
+    st = OR_EBREAKDOWN;
+  } else {
+    double rho = sqrt(rho2);
+    for (int j = 0; j < p; ++j) axmy(n, sc[j], QCOL(s, j), qp);
+    for (int64_t r = 0; r < n; ++r) qp[r] = qp[r] / rho;
+    double rpp = RM(s, p, p);
+    for (int j = 0; j < p; ++j) RM(s, j, p) = RM(s, j, p) + rpp * sc[j];
+    RM(s, p, p) = rho * rpp;
+    double rpk = (beta - sz) / rho;
+    double rr = 0.0;
+    for (int j = 0; j < p; ++j) {
+      RM(s, j, k) = zc[j];
+      rr += zc[j] * zc[j];
+    }
+    RM(s, p, k) = rpk;
+    rr += rpk * rpk;
+    double w2 = nu - rr;
+    if (!(w2 > 0.0) || !isfinite(w2)) {
+      st = OR_EBREAKDOWN;
+    } else {
+      double rkk = sqrt(w2);
+      for (int j = 0; j < p; ++j) axmy(n, zc[j], QCOL(s, j), v);
+      axmy(n, rpk, qp, v);
+      RM(s, k, k) = rkk;
+      double *q = QCOL(s, k);
+      for (int64_t r = 0; r < n; ++r) q[r] = v[r] / rkk;
+      s->k = k + 1;
+    }
+  }
+  free(sc);
+  free(zc);
+  return st;
+}
+
+/* The lagged DCGS-2's last step on its own: reorthogonalize and renormalize
+ * the newest column (one reduction, as the paper notes the last iteration of
+ * the lagged form needs), so that every column is final. */
+int or_qr_flush(or_qr *s, int variant) {
+  if (variant != OR_DCGS2_LAG) return OR_EINVAL;
+  int k = s->k;
+  if (k == 0) return OR_OK;
+  int p = k - 1;
+  int64_t n = s->n;
+  double *qp = QCOL(s, p);
+  double *sc = (double *)calloc((size_t)k, sizeof(double));
+  for (int j = 0; j < p; ++j) sc[j] = dot(n, QCOL(s, j), qp);
+  double alpha = dot(n, qp, qp);
+  s->syncs_add += 1;
+  double ss = 0.0;
+  for (int j = 0; j < p; ++j) ss += sc[j] * sc[j];
+  double rho2 = alpha - ss;
+  int st = OR_OK;
+  if (!(rho2 > 0.0) || !isfinite(rho2)) {
+    st = OR_EBREAKDOWN;
+  } else {
+    double rho = sqrt(rho2);
+    for (int j = 0; j < p; ++j) axmy(n, sc[j], QCOL(s, j), qp);
+    for (int64_t r = 0; r < n; ++r) qp[r] = qp[r] / rho;
+    double rpp = RM(s, p, p);
+    for (int j = 0; j < p; ++j) RM(s, j, p) = RM(s, j, p) + rpp * sc[j];
+    RM(s, p, p) = rho * rpp;
+  }
+  free(sc);
+  return st;
+}
+
 /* Alg. 2, QRAdd: append v (not modified) as column k of the factorization. */
 int or_qr_add(or_qr *s, int variant, unsigned flags, const double *v_in) {
   if (s->k >= s->cap) return OR_ESTATE;
@@ -201,6 +316,7 @@ int or_qr_add(or_qr *s, int variant, unsigned flags, const double *v_in) {
     case OR_CGS2: return qr_add_cgs2(s, v);
     case OR_DCGS2: return qr_add_dcgs2(s, v, flags);
     case OR_ICWY: return qr_add_icwy(s, v);
+    case OR_DCGS2_LAG: return qr_add_dcgs2_lag(s, v);
     default: return OR_EINVAL;
   }
 }
@@ -218,14 +334,40 @@ int or_qr_add(or_qr *s, int variant, unsigned flags, const double *v_in) {
  * unique QR of the retained columns.  The last row of H and the last column
  * of Q are then dropped.  No reduction is needed, except that ICWY must
  * refresh T (Sec. 3.2): T_ab = q_a^T q_b for b < a, T_aa = 1, recomputed
- * over the rotated columns in one reduction. */
-int or_qr_delete(or_qr *s, int variant) {
+ * over the rotated columns in one reduction.
+ *
+ * With OR_ICWY_T_TRANSFORM the refresh needs no reduction: the old Gram
+ * matrix S = I + L + L^T (L the strict lower part of T) is rotated like the
+ * columns of Q, S <- W^T S W with the same rotations, and its strict lower
+ * part is the new T.  The new columns 0..k-3 are combinations of the old
+ * columns 0..k-2 only (rotation j leaves column j final), whose rows of T
+ * are current, so rotations 0..k-3 applied to the leading (k-1) x (k-1)
+ * block of S give rows 0..k-3 of the new T exactly.  The last row (the
+ * newest retained column, which old column k-1 entered) is the Gram row the
+ * next QRAdd's first reduction computes before anything reads it (Alg. 4);
+ * it is zeroed here. */
+int or_qr_delete(or_qr *s, int variant, unsigned flags) {
   int k = s->k;
   if (k <= 0) return OR_ESTATE;
   if (k == 1) {
     s->k = 0;
     RM(s, 0, 0) = 0.0;
     return OR_OK;
+  }
+  int transform = variant == OR_ICWY && (flags & OR_ICWY_T_TRANSFORM);
+  int kk = k - 1;
+  double *S = NULL, *gc = NULL, *gs = NULL;
+  if (transform) {
+    S = (double *)calloc((size_t)kk * (size_t)kk, sizeof(double));
+    gc = (double *)calloc((size_t)kk, sizeof(double));
+    gs = (double *)calloc((size_t)kk, sizeof(double));
+    for (int a = 0; a < kk; ++a) {
+      S[a + (int64_t)a * kk] = 1.0;
+      for (int b = 0; b < a; ++b) {
+        S[a + (int64_t)b * kk] = TM(s, a, b);
+        S[b + (int64_t)a * kk] = TM(s, a, b);
+      }
+    }
   }
   /* shift R left by one column: H_{:,j} = R_{:,j+1} */
   for (int j = 0; j < k - 1; ++j)
@@ -245,6 +387,10 @@ int or_qr_delete(or_qr *s, int variant) {
       RM(s, j + 1, col) = -sn * hj + c * hj1;
     }
     RM(s, j + 1, j) = 0.0;
+    if (transform) {
+      gc[j] = c;
+      gs[j] = sn;
+    }
     double *qa = QCOL(s, j), *qb = QCOL(s, j + 1);
     for (int64_t r = 0; r < s->n; ++r) {
       double x = qa[r], y = qb[r];
@@ -254,7 +400,32 @@ int or_qr_delete(or_qr *s, int variant) {
   }
   for (int i = 0; i < k; ++i) RM(s, k - 1, i) = 0.0;
   s->k = k - 1;
-  if (variant == OR_ICWY) {
+  if (transform) {
+    /* S <- W^T S W, rotations 0..kk-2 (columns j, j+1, then rows j, j+1) */
+#define SM(i, j) S[(i) + (int64_t)(j) * kk]
+    for (int j = 0; j + 1 < kk; ++j) {
+      double c = gc[j], sn = gs[j];
+      for (int r = 0; r < kk; ++r) {
+        double x = SM(r, j), y = SM(r, j + 1);
+        SM(r, j) = c * x + sn * y;
+        SM(r, j + 1) = -sn * x + c * y;
+      }
+      for (int r = 0; r < kk; ++r) {
+        double x = SM(j, r), y = SM(j + 1, r);
+        SM(j, r) = c * x + sn * y;
+        SM(j + 1, r) = -sn * x + c * y;
+      }
+    }
+    for (int a = 0; a < kk; ++a) {
+      for (int b = 0; b < a; ++b) TM(s, a, b) = (a < kk - 1) ? SM(a, b) : 0.0;
+      TM(s, a, a) = 1.0;
+      for (int b = a + 1; b < s->cap; ++b) TM(s, a, b) = 0.0;
+    }
+#undef SM
+    free(S);
+    free(gc);
+    free(gs);
+  } else if (variant == OR_ICWY) {
     for (int a = 0; a < s->k; ++a) {
       for (int b = 0; b < a; ++b) TM(s, a, b) = dot(s->n, QCOL(s, b), QCOL(s, a));
       TM(s, a, a) = 1.0;
@@ -351,7 +522,7 @@ int or_aa_step(or_aa *a, const double *x, const double *g, double *x_next) {
   a->res_norm = nrm2(n, a->f);
 
   int st = OR_OK;
-  if (i > m) st = or_qr_delete(s, a->variant);
+  if (i > m) st = or_qr_delete(s, a->variant, a->flags);
   if (st == OR_OK) st = or_qr_add(s, a->variant, a->flags, df);
   if (st != OR_OK) {
     a->status = st;

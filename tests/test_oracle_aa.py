@@ -22,7 +22,7 @@ import aa_workloads as W
 import oracle as O
 
 EPS = np.finfo(np.float64).eps
-VARIANTS = ["mgs", "cgs2", "dcgs2", "icwy"]
+VARIANTS = ["mgs", "cgs2", "dcgs2", "icwy", "dcgs2_lag"]
 
 
 def spd(n, seed, shift=0.5):

@@ -28,6 +28,14 @@ MUTANTS = [
     ("backsolve_index", "acc -= R[a + (int64_t)b * cap] * gamma[b];",
      "acc -= R[b + (int64_t)a * cap] * gamma[b];"),
     ("mgs_stale_update", "axmy(s->n, rj, QCOL(s, j), v);", "(void)0;"),
+    # ICWY's T after QRDelete by rotating the old Gram matrix
+    ("T_transform_row_sign", "SM(j + 1, r) = -sn * x + c * y;", "SM(j + 1, r) = sn * x + c * y;"),
+    ("T_transform_no_row_rotation", "SM(j, r) = c * x + sn * y;", "(void)x;"),
+    # DCGS-2 with the normalization lagged
+    ("lag_R_unscaled", "RM(s, j, p) = RM(s, j, p) + rpp * sc[j];",
+     "RM(s, j, p) = RM(s, j, p) + sc[j];"),
+    ("lag_rpk_no_correction", "double rpk = (beta - sz) / rho;", "double rpk = beta / rho;"),
+    ("lag_norm_sign", "double rho2 = alpha - ss;", "double rho2 = alpha + ss;"),
 ]
 
 
@@ -115,6 +123,41 @@ def _run_pins(so):
             Fn = np.column_stack([Qb @ base.Rk(), w])
             if np.linalg.norm(Fn - q.Qk() @ q.Rk()) > 1e-13 * np.linalg.norm(Fn):
                 return False
+        # ICWY with T rotated after QRDelete: T stays the Gram of the basis
+        q = O.QR(n, 6, "icwy", O.ICWY_T_TRANSFORM)
+        for j in range(6):
+            if q.add(F2[:, j]) != 0:
+                return False
+        if q.delete() != 0:
+            return False
+        Gq = q.Qk().T @ q.Qk()
+        Tq = q.Tk()
+        for a in range(1, 4):
+            if np.abs(Tq[a, :a] - Gq[a, :a]).max() > 1e-13:
+                return False
+        # lagged DCGS-2 on the same non-orthonormal basis (its delayed
+        # corrections s ~ 1e-4 are large here): Q R = F, the reorthogonalized
+        # previous column has unit norm, the new column is orthogonal to it
+        q = O.QR(n, 7, "dcgs2_lag")
+        q.Q[:, :6] = Qb
+        q.R[:6, :6] = base.Rk()
+        q.s.k = 6
+        if q.add(w) != 0:
+            return False
+        Fn = np.column_stack([Qb @ base.Rk(), w])
+        if np.linalg.norm(Fn - q.Qk() @ q.Rk()) > 1e-13 * np.linalg.norm(Fn):
+            return False
+        if abs(np.linalg.norm(q.Q[:, 5]) - 1.0) > 1e-10 or abs(q.Q[:, 5] @ q.Q[:, 6]) > 1e-6:
+            return False
+        # lagged DCGS-2: Q R = F after each add, orthonormal after the last step
+        q = O.QR(n, m, "dcgs2_lag")
+        for j in range(m):
+            if q.add(F[:, j]) != 0:
+                return False
+            if np.linalg.norm(F[:, : j + 1] - q.Qk() @ q.Rk()) > 1e-13 * np.linalg.norm(F):
+                return False
+        if q.flush() != 0 or np.linalg.norm(np.eye(m) - q.Qk().T @ q.Qk()) > 1e-13:
+            return False
         # whole loop: AA == GMRES on a small SPD system
         A = rng.standard_normal((20, 20))
         A = A @ A.T / 20 + np.eye(20)

@@ -23,6 +23,8 @@ import oracle as O
 
 EPS = np.finfo(np.float64).eps
 VARIANTS = ["mgs", "cgs2", "dcgs2", "icwy"]
+# with the delayed CGS-2 whose normalization is lagged too (Sec. 3.4)
+VARIANTS_ALL = VARIANTS + ["dcgs2_lag"]
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
@@ -51,7 +53,7 @@ def fill(variant, F, flags=0):
     return q
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("variant", VARIANTS_ALL)
 @pytest.mark.parametrize("kappa", [1e1, 1e4, 1e7])
 def test_qr_equals_F_after_adds(variant, kappa):
     F = graded_matrix(300, 8, kappa, seed=11)
@@ -63,7 +65,7 @@ def test_qr_equals_F_after_adds(variant, kappa):
     assert err <= 10 * 8 * EPS, err
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("variant", VARIANTS_ALL)
 def test_qr_equals_F_through_window_recycling(variant):
     """Add 3m columns through a window of m: delete the oldest when full."""
     n, m = 257, 5
@@ -110,7 +112,7 @@ def test_mgs_loss_grows_with_kappa():
     assert loss("cgs2", 1e10) <= 50 * m * EPS
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("variant", VARIANTS_ALL)
 @pytest.mark.parametrize("k", [0, 1, 2, 3, 5, 9])
 def test_new_column_matches_householder(variant, k):
     """Exactly orthonormal Q and Gaussian v: every variant returns the last
@@ -129,7 +131,7 @@ def test_new_column_matches_householder(variant, k):
     assert np.allclose(q.R[: k + 1, k], Rh[:, k], rtol=0, atol=1e-13 * np.abs(Rh).max())
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("variant", VARIANTS_ALL)
 @pytest.mark.parametrize("m", [2, 3, 6])
 def test_delete_gives_unique_R_of_kept_columns(variant, m):
     n = 90
@@ -158,7 +160,7 @@ def test_delete_single_column_and_empty_window_errors():
     assert q.add(np.ones(10) * 3) == O.ESTATE  # window full
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("variant", VARIANTS_ALL)
 def test_breakdown_is_reported(variant):
     q = O.QR(16, 3, variant)
     assert q.add(np.zeros(16)) == O.EBREAKDOWN
@@ -179,7 +181,7 @@ def _golden_syncs():
     return rows
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("variant", VARIANTS_ALL)
 @pytest.mark.parametrize("m", [1, 2, 3, 4, 7, 12])
 def test_sync_counts_match_paper(variant, m):
     a, b, c, d, rec, dele = _golden_syncs()[variant]
@@ -228,7 +230,7 @@ def test_icwy_equals_mgs_coefficients(kappa):
     assert np.allclose(cols["icwy"], r, rtol=0, atol=100 * k * EPS * np.linalg.norm(v))
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("variant", VARIANTS_ALL)
 def test_qr_equals_F_with_nonorthonormal_basis(variant):
     """Each variant's update satisfies Q R = F as an algebraic identity, even
     when the stored basis has lost orthogonality (here ~1e-4, an MGS basis of
