@@ -45,8 +45,22 @@ typedef struct aa_ctx aa_ctx;
 typedef struct aa_batch aa_batch;
 typedef struct aa_mlp aa_mlp;
 
-/* QRAdd variants (Sec. 3): Alg. 3, Alg. 5, Alg. 6, Alg. 4. */
-typedef enum { AA_MGS = 0, AA_CGS2 = 1, AA_DCGS2 = 2, AA_ICWY = 3 } aa_variant;
+/* QRAdd variants (Sec. 3): Alg. 3, Alg. 5, Alg. 6, Alg. 4, and the delayed
+ * CGS-2 whose normalization is lagged as well (the stable form Sec. 3.4
+ * describes after Swirydowicz et al. and Bielich et al., which the paper does
+ * not run in AA).  AA_DCGS2_LAG adds a column with ONE reduction: the block
+ * dot products [Q^T v | Q^T q_{k-1} | v^T v] reorthogonalize and normalize the
+ * previous column q_{k-1} (its correction s = Q_{:,0:k-2}^T q_{k-1}, its norm
+ * sqrt(q_{k-1}^T q_{k-1} - s^T s)), project v once on the updated basis and
+ * give the new column's norm by Pythagoras, R_kk = sqrt(v^T v - ||R_{0:k-1,k}||^2),
+ * with no reduction over the new column; one more pass writes both columns.
+ * Q R = F_i holds after every add and the LSP solve uses the newest column
+ * as it stands (orthogonalized once); its reorthogonalization happens in the
+ * next add.  A non-positive squared norm (the new column numerically in the
+ * span of Q) latches AA_EBREAKDOWN.  Grid-wide passes only (no one-workgroup
+ * step, no batched path, no AA_FUSE_DELETE). */
+typedef enum { AA_MGS = 0, AA_CGS2 = 1, AA_DCGS2 = 2, AA_ICWY = 3,
+               AA_DCGS2_LAG = 4 } aa_variant;
 
 typedef enum {
   AA_OK = 0,
@@ -62,6 +76,17 @@ enum {
   /* Alg. 6 read literally: R_{0:k-2,k-1} += s.  Default adds R_{k-1,k-1} s,
    * which keeps Q R = F_i (the factorization Alg. 2 relies on). */
   AA_DCGS2_LITERAL = 1u << 1,
+  /* ICWY: after QRDelete, update T without a reduction (the alternative
+   * reading of Sec. 3.2's T update): the Givens kernel rotates the old Gram
+   * matrix I + L + L^T of the columns 0..k-2 like the columns of Q and keeps
+   * its strict lower rows 0..k-3 as the new T; the rotation pass then streams
+   * Q without the Gram.  The last row of T (the column that old column k-1
+   * entered) is recomputed by the next QRAdd's first reduction before any
+   * read (Alg. 4), so aa_get_qr reports rows 0..k-2 only as current.  One
+   * reduction fewer per recycled iteration.  Grid-wide passes only; with
+   * AA_FUSE_DELETE the fused Gram refreshes T instead.  Not for the batched
+   * entry points (AA_EINVAL). */
+  AA_ICWY_T_TRANSFORM = 1u << 2,
   /* Alg. 6: reorthogonalize the previous column when m_i >= 3 instead of the
    * printed m_i > 3. */
   AA_DCGS2_GUARD_GE3 = 1u << 4,

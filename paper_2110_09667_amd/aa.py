@@ -13,9 +13,10 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaa.so")
 
-MGS, CGS2, DCGS2, ICWY = 0, 1, 2, 3
-VARIANTS = {"mgs": MGS, "cgs2": CGS2, "dcgs2": DCGS2, "icwy": ICWY}
+MGS, CGS2, DCGS2, ICWY, DCGS2_LAG = 0, 1, 2, 3, 4
+VARIANTS = {"mgs": MGS, "cgs2": CGS2, "dcgs2": DCGS2, "icwy": ICWY, "dcgs2_lag": DCGS2_LAG}
 DCGS2_LITERAL = 1 << 1
+ICWY_T_TRANSFORM = 1 << 2
 DCGS2_GUARD_GE3 = 1 << 4
 FUSE_RHS = 1 << 3
 FUSE_DELETE = 1 << 5

@@ -35,6 +35,7 @@ struct aa_ctx {
   BInst* d_binst = nullptr;
   BState* d_bstate = nullptr;
   int64_t fused_max = 0;  // set by aa_init: kFusedWork / m
+  bool one_wg_ok = true;  // the variant and flags have a one-workgroup step
   // steady-state iterations replayed as HIP graphs (aa_set_graph): one per
   // ring-slot phase (i - 1) mod m, valid for the caller pointers it captured
   struct StepGraph {
@@ -110,7 +111,10 @@ Layout make_layout(int64_t n, int m, unsigned flags) {
   return L;
 }
 
-bool valid_variant(int v) { return v >= AA_MGS && v <= AA_ICWY; }
+bool valid_variant(int v) { return v >= AA_MGS && v <= AA_DCGS2_LAG; }
+
+// Variants whose first QRAdd pass the fused delete can take over.
+bool fuse_delete_ok(int v) { return v == AA_CGS2 || v == AA_DCGS2 || v == AA_ICWY; }
 
 aa_status hip_ok(hipError_t e) { return e == hipSuccess ? AA_OK : AA_EHIP; }
 
@@ -324,6 +328,33 @@ aa_status qr_add_impl(aa_ctx* c, const double* v, const double* f = nullptr,
         c->syncs_add += first_done ? 1 : 2;
         break;
       }
+      case AA_DCGS2_LAG: {
+        // DCGS-2 with the normalization lagged (Sec. 3.4): one reduction
+        // [Q^T v | Q^T q_{k-1} | v^T v (| Q^T f, v^T f)] finishes the previous
+        // column and projects v; the update pass writes both columns already
+        // normalized (no reduction, no scale pass).
+        const int p = k - 1;
+        d.nx = k;
+        d.y = c->Q + (int64_t)p * c->ldq;
+        d.ny = k;
+        d.xx = 1;
+        Tail tl = tail(TAIL_DCGS2_LAG, k);
+        tl.idx = 2 * k;
+        if (fuse) {
+          d.z = f; d.nz = k; d.xz = 1;
+          tl.rhs = 1; tl.zoff = 2 * k; tl.idx = 3 * k;
+        }
+        chk(timed(c, AA_K_DOTS, k + 1 + zf, [&] { return launch_dots(d, c->sm, tl, G, st); }));
+        UpdArgs ub = u;
+        ub.v = v; ub.out = slotk; ub.c1 = c->sm.coef0; ub.s = c->sm.coef1;
+        ub.dcgs2_p = p; ub.reorth = 1; ub.j0 = 0; ub.nc = p;
+        ub.pdiv = c->sm.scal + S_RHO; ub.odiv = c->sm.scal + S_RKK;
+        chk(timed(c, AA_K_UPDATE, k + 3, [&] { return launch_update(ub, c->sm, tail(TAIL_NONE, k), G, st); }));
+        c->syncs_add += 1;
+        if (e != hipSuccess) return AA_EHIP;
+        c->k = k + 1;
+        return AA_OK;
+      }
       default:
         return AA_EINVAL;
     }
@@ -346,9 +377,13 @@ aa_status qr_delete_impl(aa_ctx* c, bool refresh_next) {
     c->k = 0;
     return AA_OK;
   }
-  hipError_t e = timed(c, AA_K_GIVENS, 0, [&] { return launch_givens(c->sm, k, c->stream); });
+  // ICWY with AA_ICWY_T_TRANSFORM: T follows the rotations in the Givens
+  // kernel (no reduction); otherwise the rotation pass refreshes it.
+  const bool transform = c->variant == AA_ICWY && (c->flags & AA_ICWY_T_TRANSFORM);
+  hipError_t e = timed(c, AA_K_GIVENS, 0,
+                       [&] { return launch_givens(c->sm, k, c->stream, transform); });
   if (e != hipSuccess) return AA_EHIP;
-  const bool gram = c->variant == AA_ICWY;
+  const bool gram = c->variant == AA_ICWY && !transform;
   const int drop = gram && refresh_next ? 1 : 0;
   RotArgs r{c->Q, c->ldq, c->n, k, c->sm.givens, gram ? 1 : 0, nullptr, nullptr, 0, drop};
   const int ng = gram_cols(r);  // columns of the Gram
@@ -441,6 +476,7 @@ double add_vectors(int variant, unsigned flags, int k) {
     case AA_MGS: return 4.0 * k + 3;
     case AA_CGS2: return 3.0 * k + 6;
     case AA_ICWY: return 2.0 * k + 5;
+    case AA_DCGS2_LAG: return 2.0 * k + 4;
     default: {
       const int m_i = k + 1;
       const bool reorth = (flags & AA_DCGS2_GUARD_GE3) ? (m_i >= 3) : (m_i > 3);
@@ -454,6 +490,7 @@ int64_t add_syncs(int variant, int k) {
   switch (variant) {
     case AA_MGS: return k + 1;
     case AA_CGS2: return 3;
+    case AA_DCGS2_LAG: return 1;
     default: return 2;
   }
 }
@@ -559,7 +596,9 @@ aa_status aa_init(aa_ctx** ctx, int64_t n, int m, int variant, unsigned flags,
   c->n = n;
   c->ldq = L.ldq;
   c->m = m;
-  c->fused_max = kFusedWork / m;
+  // the one-workgroup step implements Algs. 3-6 with the paper's T refresh
+  c->one_wg_ok = variant != AA_DCGS2_LAG && !(flags & AA_ICWY_T_TRANSFORM);
+  c->fused_max = c->one_wg_ok ? kFusedWork / m : 0;
   c->cap = m;
   c->variant = variant;
   c->flags = flags;
@@ -644,7 +683,7 @@ static aa_status step_enqueue(aa_ctx* c, const double* x, const double* g,
   aa_status s = AA_OK;
   bool rhs_done = false;
   const bool fuse_rhs = (c->flags & AA_FUSE_RHS) != 0;
-  if (i > m && c->variant != AA_MGS && (c->flags & AA_FUSE_DELETE) && c->k >= 2 &&
+  if (i > m && fuse_delete_ok(c->variant) && (c->flags & AA_FUSE_DELETE) && c->k >= 2 &&
       c->k - 1 + (fuse_rhs ? 2 : 1) <= 64) {
     // QRDelete + QRAdd of Delta f_{i-1} with their first reductions merged
     s = fused_delete_add(c, c->W, fuse_rhs ? c->f_prev : nullptr, &rhs_done);
@@ -883,7 +922,7 @@ aa_status aa_profile_read(aa_ctx* c, int kind, double* ms, int64_t* launches, do
 aa_status aa_set_fused_threshold(aa_ctx* c, int64_t n_max) {
   if (c) drop_graphs(c);
   if (!c || n_max < 0) return AA_EINVAL;
-  c->fused_max = n_max;
+  c->fused_max = c->one_wg_ok ? n_max : 0;
   return AA_OK;
 }
 

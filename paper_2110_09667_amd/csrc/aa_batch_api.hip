@@ -133,8 +133,8 @@ extern "C" {
 
 aa_status aa_batch_workspace_size(int count, const aa_batch_instance* inst, int variant,
                                   unsigned flags, size_t* bytes) {
-  (void)flags;
   if (count < 1 || !inst || !bytes || variant < AA_MGS || variant > AA_ICWY) return AA_EINVAL;
+  if (flags & AA_ICWY_T_TRANSFORM) return AA_EINVAL;  // one-workgroup step: Gram refresh only
   const bool learned = (flags & AA_BATCH_LEARNED) != 0;
   size_t tot = header_bytes(count, learned);
   for (int j = 0; j < count; ++j) {

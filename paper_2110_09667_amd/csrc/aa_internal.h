@@ -23,7 +23,9 @@ constexpr int kMaxRedAll = kMaxPairs > kMaxRed ? kMaxPairs : kMaxRed;
 constexpr int kFinWG = 1024;         // threads of the finalize kernel
 
 // Scalar slots in the small device block.
-enum Scal : int { S_RES = 0, S_RES0 = 1, S_STEP = 2, S_COUNT = 8 };
+// S_RHO, S_RKK: the lagged DCGS-2's divisors of its update pass (the norm of
+// the reorthogonalized previous column and the new column's norm).
+enum Scal : int { S_RES = 0, S_RES0 = 1, S_STEP = 2, S_RHO = 3, S_RKK = 4, S_COUNT = 8 };
 
 // What the last-arriving workgroup does with the reduced values.
 enum TailOp : int {
@@ -40,8 +42,10 @@ enum TailOp : int {
   TAIL_FIRST,     // scal[S_RES0] = scal[S_RES] = red[0], scal[S_STEP] = red[1]
   TAIL_STEP,      // scal[S_STEP] = red[0]
   TAIL_GRAM,      // T strict lower from pair sums
-  TAIL_GRAM_ADD   // pairs of [Q v (f)]: T refresh (gram_t), then the QRAdd's
+  TAIL_GRAM_ADD,  // pairs of [Q v (f)]: T refresh (gram_t), then the QRAdd's
                   // first-pass tail `inner` on the rearranged values (finalize)
+  TAIL_DCGS2_LAG  // lagged DCGS-2: reorthogonalize and normalize the previous
+                  // column, project the new one (R, coef0, coef1, S_RHO, S_RKK)
 };
 
 // Device-resident small dense state (pointers into the workspace).
@@ -75,13 +79,15 @@ struct Tail {
 // ---- streaming passes -------------------------------------------------------
 
 // red[j] = Q_j^T x (j < nx); red[nx + j] = Q_j^T y (j < ny);
-// red[nx + ny + j] = Q_j^T z (j < nz); red[nx + ny + nz] = x^T x
+// red[nx + ny + j] = Q_j^T z (j < nz); red[nx + ny + nz] = x^T x (xx), then
+// x^T z (xz, needs nz > 0)
 struct DotsArgs {
   const double* Q; int64_t ldq; int64_t n;
   const double* x; int nx;
   const double* y; int ny;
   int xx;
   const double* z; int nz;
+  int xz;
 };
 
 // out = v - sum_{j0 <= j < j0+nc} Q_j (c1[j] + c2[j]) evaluated as
@@ -103,6 +109,10 @@ struct UpdArgs {
   int reorth;
   const double* s;       // DCGS-2 reorthogonalization coefficients
   const double* rhsv;    // may be null: add out^T rhsv after the norm
+  // lagged DCGS-2 (DCGS-2 mode): divide q'_p by *pdiv before use and the
+  // output by *odiv (device scalars; null: no division)
+  const double* pdiv;
+  const double* odiv;
 };
 
 struct Cgs2bArgs {       // y = v - Q s (registers), red[j] = Q_j^T y
@@ -223,7 +233,8 @@ bool profile_mid_used();
 hipError_t launch_dots(const DotsArgs&, const Small&, const Tail&, int grid, hipStream_t);
 hipError_t launch_update(const UpdArgs&, const Small&, const Tail&, int grid, hipStream_t);
 hipError_t launch_cgs2b(const Cgs2bArgs&, const Small&, const Tail&, int grid, hipStream_t);
-hipError_t launch_givens(const Small&, int k, hipStream_t);
+// transform: also rotate ICWY's T like the columns (AA_ICWY_T_TRANSFORM)
+hipError_t launch_givens(const Small&, int k, hipStream_t, bool transform = false);
 hipError_t launch_rotate(const RotArgs&, const Small&, const Tail&, int grid, hipStream_t);
 hipError_t launch_scale(const ScaleArgs&, const Small&, hipStream_t);
 hipError_t launch_history(const HistArgs&, const Small&, const Tail&, int grid, hipStream_t);

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kWG) void k_dots(DotsArgs a, Small sm) {
 #endif
 template <int KQ, int NR>
 __global__ __launch_bounds__(kWG) void k_dots_reg(DotsArgs a, Small sm) {
-  constexpr int STR = NR * KQ + 1;  // nx + ny + nz + xx <= NR KQ + 1
+  constexpr int STR = NR * KQ + 2;  // nx + ny + nz + xx + xz <= NR KQ + 2
   __shared__ double s_acc[kWaves * STR];
   lds_zero(s_acc, kWaves * STR);
   __syncthreads();
@@ -139,9 +139,13 @@ __global__ __launch_bounds__(kWG) void k_cgs2b(Cgs2bArgs a, Small sm) {
   publish(sm, a.k, s_acc, KMAX);
 }
 
-__global__ __launch_bounds__(64) void k_givens(Small sm, int k) {
+__global__ __launch_bounds__(64) void k_givens(Small sm, int k, int transform) {
   __shared__ double H[kMaxCols * kMaxCols];
   givens_body(sm, k, H);
+  if (transform) {
+    __syncthreads();  // H is free once R is written: it holds the Gram matrix
+    t_transform_body(sm, k, H);
+  }
 }
 
 __global__ __launch_bounds__(kWG) void k_rotate(RotArgs a, Small sm) {
@@ -368,7 +372,8 @@ hipError_t launch_dots(const DotsArgs& a, const Small& sm, const Tail& t, int gr
                        hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
   // every vector the counts name must exist
-  if (!a.x || (a.ny > 0 && !a.y) || (a.nz > 0 && !a.z)) return hipErrorInvalidValue;
+  if (!a.x || (a.ny > 0 && !a.y) || (a.nz > 0 && !a.z) || (a.xz && a.nz < 1))
+    return hipErrorInvalidValue;
   // one round of resident workgroups at most; the finalize sums `grid` partials
   auto clamp_launch = [&](const void* kern, auto launch) {
     const int g = clamp_resident(grid, kern, kWG, 0);
@@ -422,7 +427,7 @@ hipError_t launch_dots(const DotsArgs& a, const Small& sm, const Tail& t, int gr
     grid = clamp_launch(reinterpret_cast<const void*>(&k_dots), [&](int g) {
       hipLaunchKernelGGL(k_dots, dim3(g), dim3(kWG), 0, st, a, sm);
     });
-  return launch_finalize(sm, t, a.nx + a.ny + a.nz + (a.xx ? 1 : 0), grid, st);
+  return launch_finalize(sm, t, a.nx + a.ny + a.nz + (a.xx ? 1 : 0) + (a.xz ? 1 : 0), grid, st);
 }
 
 hipError_t launch_update(const UpdArgs& a, const Small& sm, const Tail& t, int grid,
@@ -430,6 +435,7 @@ hipError_t launch_update(const UpdArgs& a, const Small& sm, const Tail& t, int g
   (void)hipGetLastError();  // drop a stale error left by an earlier call
   grid = clamp_resident(grid, reinterpret_cast<const void*>(&k_update), kWG, 0);
   hipLaunchKernelGGL(k_update, dim3(grid), dim3(kWG), 0, st, a, sm);
+  if (update_nred(a) == 0) return hipGetLastError();  // nothing reduced: no Sync
   return launch_finalize(sm, t, update_nred(a), grid, st);
 }
 
@@ -456,9 +462,9 @@ hipError_t launch_cgs2b(const Cgs2bArgs& a, const Small& sm, const Tail& t, int 
   return launch_finalize(sm, t, a.k, grid, st);
 }
 
-hipError_t launch_givens(const Small& sm, int k, hipStream_t st) {
+hipError_t launch_givens(const Small& sm, int k, hipStream_t st, bool transform) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
-  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, sm, k);
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, sm, k, transform ? 1 : 0);
   return hipGetLastError();
 }
 

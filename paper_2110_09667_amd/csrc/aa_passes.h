@@ -147,6 +147,71 @@ __device__ inline void run_tail(const Small& sm, const Tail& t, const double* re
         for (int b = tid; b < a; b += nthr) T[a + (size_t)b * cap] = red[a * (a - 1) / 2 + b];
       break;
     }
+    case TAIL_DCGS2_LAG: {
+      // DCGS-2 with the normalization lagged (Sec. 3.4), p = k-1 the newest
+      // column.  red: Q^T v (z_j, j < p; beta at p), Q^T q_p (s_j; alpha at
+      // k + p), v^T v at idx; with rhs Q^T f (c'_j; phi at zoff + p) and v^T f
+      // at idx + 1.  One thread, in the order of the definition:
+      //   rho = sqrt(alpha - s^T s); R_{0:p-1,p} += R_pp s; R_pp *= rho;
+      //   R_{0:p-1,k} = z; R_pk = (beta - s^T z) / rho;
+      //   R_kk = sqrt(nu - ||R_{0:p,k}||^2)   (no reduction over the new column).
+      // The update pass then forms q_p = (q_p - Q s) / rho and
+      // q_k = (v - Q z - q_p R_pk) / R_kk.
+      const int p = k - 1;
+      if (tid == 0) {
+        double ss = 0.0, sz = 0.0;
+        for (int j = 0; j < p; ++j) {
+          const double sj = red[k + j];
+          ss += sj * sj;
+          sz += sj * red[j];
+        }
+        const double rho2 = red[k + p] - ss;
+        const double rho = sqrt(rho2);
+        const double rpp = R[p + (size_t)p * cap];
+        for (int j = 0; j < p; ++j) R[j + (size_t)p * cap] += rpp * red[k + j];
+        R[p + (size_t)p * cap] = rho * rpp;
+        const double rpk = (red[p] - sz) / rho;
+        double rr = 0.0;
+        for (int j = 0; j < p; ++j) {
+          const double zj = red[j];
+          R[j + (size_t)k * cap] = zj;
+          rr += zj * zj;
+          sm.coef0[j] = zj;
+          sm.coef1[j] = red[k + j];
+        }
+        R[p + (size_t)k * cap] = rpk;
+        sm.coef0[p] = rpk;
+        rr += rpk * rpk;
+        const double w2 = red[t.idx] - rr;
+        const double rkk = sqrt(w2);
+        R[k + (size_t)k * cap] = rkk;
+        sm.scal[S_RHO] = rho;
+        sm.scal[S_RKK] = rkk;
+        if (!(rho2 > 0.0) || !isfinite(rho2) || !(w2 > 0.0) || !isfinite(w2))
+          *sm.status = AA_EBREAKDOWN;
+        if (t.rhs) {
+          // c = Q^T f of the grown basis from the same reduction: c_j = c'_j,
+          // c_p = (phi - s^T c') / rho, c_k = (v^T f - z^T c' - R_pk c_p) / R_kk
+          double sc = 0.0, zc = 0.0;
+          for (int j = 0; j < p; ++j) {
+            const double cj = red[t.zoff + j];
+            sm.gamma[j] = cj;
+            sc += red[k + j] * cj;
+            zc += red[j] * cj;
+          }
+          const double cp = (red[t.zoff + p] - sc) / rho;
+          sm.gamma[p] = cp;
+          sm.gamma[k] = (red[t.idx + 1] - zc - rpk * cp) / rkk;
+        }
+      }
+      if (t.rhs) {
+        __syncthreads();
+        const double x = lane <= k ? sm.gamma[lane] : 0.0;
+        __syncthreads();
+        rhs_backsolve(sm, k + 1, x);
+      }
+      break;
+    }
     default:
       break;
   }
@@ -180,14 +245,14 @@ __device__ __forceinline__ void lds_zero(double* p, int n) {
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ int dots_nred(const DotsArgs& a) {
-  return a.nx + a.ny + a.nz + (a.xx ? 1 : 0);
+  return a.nx + a.ny + a.nz + (a.xx ? 1 : 0) + (a.xz ? 1 : 0);
 }
 
 __device__ inline void dots_body(const DotsArgs& a, int64_t t0, int64_t ts, double* acc) {
   const int lane = threadIdx.x & 63;
   int nq = a.nx > a.ny ? a.nx : a.ny;
   if (a.nz > nq) nq = a.nz;
-  double sxx = 0.0;  // this lane's share of x^T x
+  double sxx = 0.0, sxz = 0.0;  // this lane's share of x^T x, x^T z
   for_tiles(a.n, t0, ts, [&](int64_t b2, auto full) {
     constexpr bool F = decltype(full)::value;
     double2 xv[kPairs], yv[kPairs], zv[kPairs];
@@ -195,6 +260,7 @@ __device__ inline void dots_body(const DotsArgs& a, int64_t t0, int64_t ts, doub
     if (a.ny > 0) ld2<F>(yv, a.y, b2, a.n);
     if (a.nz > 0) ld2<F>(zv, a.z, b2, a.n);
     if (a.xx) sxx += dot2(xv, xv);
+    if (a.xz) sxz += dot2(xv, zv);
     for (int j0 = 0; j0 < nq; j0 += kGroup) {
       double2 q[kGroup][kPairs];
 #pragma unroll
@@ -251,6 +317,10 @@ __device__ inline void dots_body(const DotsArgs& a, int64_t t0, int64_t ts, doub
     const double p = wave_sum(sxx);
     if (lane == 0) acc[a.nx + a.ny + a.nz] += p;
   }
+  if (a.xz) {
+    const double p = wave_sum(sxz);
+    if (lane == 0) acc[a.nx + a.ny + a.nz + (a.xx ? 1 : 0)] += p;
+  }
 }
 
 // Register-accumulated block dot products for at most KQ columns and NR
@@ -271,7 +341,7 @@ __device__ inline void dots_reg_body(const DotsArgs& a, int64_t t0, int64_t ts, 
   for (int r = 0; r < NR; ++r)
 #pragma unroll
     for (int i = 0; i < KQ; ++i) s[r][i] = 0.0;
-  double sxx = 0.0;
+  double sxx = 0.0, sxz = 0.0;
   for_tiles(a.n, t0, ts, [&](int64_t b2, auto full) {
     constexpr bool F = decltype(full)::value;
     double2 rv[NR][kPairs];
@@ -287,6 +357,9 @@ __device__ inline void dots_reg_body(const DotsArgs& a, int64_t t0, int64_t ts, 
       else zero2(rv[2]);
     }
     if (a.xx) sxx += dot2(rv[0], rv[0]);
+    if constexpr (NR > 2) {
+      if (a.xz) sxz += dot2(rv[0], rv[2]);
+    }
 #pragma unroll
     for (int j0 = 0; j0 < KQ; j0 += kGroup) {
       if (j0 < nq) {
@@ -316,6 +389,10 @@ __device__ inline void dots_reg_body(const DotsArgs& a, int64_t t0, int64_t ts, 
   if (a.xx) {
     const double p = wave_sum(sxx);
     if (lane == 0) acc[a.nx + a.ny + a.nz] = p;
+  }
+  if (a.xz) {
+    const double p = wave_sum(sxz);
+    if (lane == 0) acc[a.nx + a.ny + a.nz + (a.xx ? 1 : 0)] = p;
   }
 }
 
@@ -367,6 +444,7 @@ __device__ inline void update_body(const UpdArgs& a, const double* s_c1, const d
   const int lane = threadIdx.x & 63;
   const int inorm = a.dotcol >= 0 ? 1 : 0;
   const double* c2 = a.c2 ? s_c2 : nullptr;
+  const double pdv = a.pdiv ? *a.pdiv : 1.0, odv = a.odiv ? *a.odiv : 1.0;
   double sdot = 0.0, snrm = 0.0, srhs = 0.0;  // this lane's running sums
   for_tiles(a.n, t0, ts, [&](int64_t b2, auto full) {
     constexpr bool F = decltype(full)::value;
@@ -387,6 +465,13 @@ __device__ inline void update_body(const UpdArgs& a, const double* s_c1, const d
           qp[i].x -= acc2[i].x;
           qp[i].y -= acc2[i].y;
         }
+        if (a.pdiv) {  // lagged DCGS-2: the normalization of q_p, one add late
+#pragma unroll
+          for (int i = 0; i < kPairs; ++i) {
+            qp[i].x /= pdv;
+            qp[i].y /= pdv;
+          }
+        }
         st2<F>(qp, a.Qw + (int64_t)p * a.ldq, b2, a.n);
       }
       const double cp = s_c1[p];
@@ -394,6 +479,13 @@ __device__ inline void update_body(const UpdArgs& a, const double* s_c1, const d
       for (int i = 0; i < kPairs; ++i) {
         o[i].x = (o[i].x - acc1[i].x) - qp[i].x * cp;
         o[i].y = (o[i].y - acc1[i].y) - qp[i].y * cp;
+      }
+      if (a.odiv) {
+#pragma unroll
+        for (int i = 0; i < kPairs; ++i) {
+          o[i].x /= odv;
+          o[i].y /= odv;
+        }
       }
     } else {
       combine_cols<F>(a.Q, a.ldq, b2, a.n, a.j0, a.j0 + a.nc, s_c1, c2, acc1, acc2);
@@ -548,6 +640,45 @@ __device__ inline void givens_body(const Small& sm, int k, double* H) {
   for (int idx = tid; idx < k * k; idx += nthr) {
     const int i = idx % k, j = idx / k;
     sm.R[i + (size_t)j * cap] = (i < nc && j < nc && i <= j) ? H[i + j * k] : 0.0;
+  }
+}
+
+// ICWY's T after QRDelete without a reduction (AA_ICWY_T_TRANSFORM): the old
+// Gram matrix S = I + L + L^T of columns 0..k-2 (L the strict lower part of T,
+// whose rows 0..k-2 are current) is rotated like the columns of Q,
+// S <- W^T S W by rotations 0..k-3 (column pair j, j+1, then row pair j, j+1);
+// its strict lower rows 0..k-3 are the new T's (the new columns 0..k-3 mix old
+// columns 0..k-2 only).  The last row belongs to the column old column k-1
+// entered; the next QRAdd's first reduction recomputes it before any read
+// (Alg. 4), so it is left alone.  After givens_body (coefficients in
+// sm.givens); S: (k-1)^2 doubles of LDS; every thread must call.
+__device__ inline void t_transform_body(const Small& sm, int k, double* S) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int cap = sm.cap, kk = k - 1;
+  if (kk < 3) return;  // rows 0..kk-2 of a strict lower part: nothing below row 0
+  for (int idx = tid; idx < kk * kk; idx += nthr) {
+    const int a = idx % kk, b = idx / kk;
+    S[idx] = a == b ? 1.0 : (a > b ? sm.T[a + (size_t)b * cap] : sm.T[b + (size_t)a * cap]);
+  }
+  __syncthreads();
+  for (int j = 0; j + 1 < kk; ++j) {
+    const double c = sm.givens[j], s = sm.givens[cap + j];
+    for (int r = tid; r < kk; r += nthr) {
+      const double x = S[r + j * kk], y = S[r + (j + 1) * kk];
+      S[r + j * kk] = c * x + s * y;
+      S[r + (j + 1) * kk] = -s * x + c * y;
+    }
+    __syncthreads();
+    for (int r = tid; r < kk; r += nthr) {
+      const double x = S[j + r * kk], y = S[(j + 1) + r * kk];
+      S[j + r * kk] = c * x + s * y;
+      S[(j + 1) + r * kk] = -s * x + c * y;
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < kk * kk; idx += nthr) {
+    const int a = idx % kk, b = idx / kk;
+    if (b < a && a < kk - 1) sm.T[a + (size_t)b * cap] = S[idx];
   }
 }
 
