@@ -19,12 +19,15 @@ namespace aa {
 
 // Back substitution R gamma = c (Alg. 2, last line) by one wave: lane l < k1
 // holds c_l in x on entry.  c is also kept in coef1 (free after QRAdd; the
-// learned step reads it as a feature).  Threads past the first wave return.
-__device__ __forceinline__ void rhs_backsolve(const Small& sm, int k1, double x) {
+// learned step reads it as a feature) unless keep_c is false (the lagged
+// DCGS-2 solves before its update pass, which still reads coef1).  Threads
+// past the first wave return.
+__device__ __forceinline__ void rhs_backsolve(const Small& sm, int k1, double x,
+                                              bool keep_c = true) {
   const int tid = threadIdx.x, lane = tid & 63;
   if (tid >= 64) return;
   const int cap = sm.cap;
-  if (lane < k1) sm.coef1[lane] = x;
+  if (keep_c && lane < k1) sm.coef1[lane] = x;
   double gam = 0.0;
   for (int a = k1 - 1; a >= 0; --a) {
     const double ga = __shfl(x, a, 64) / sm.R[a + (size_t)a * cap];
@@ -208,7 +211,7 @@ __device__ inline void run_tail(const Small& sm, const Tail& t, const double* re
         __syncthreads();
         const double x = lane <= k ? sm.gamma[lane] : 0.0;
         __syncthreads();
-        rhs_backsolve(sm, k + 1, x);
+        rhs_backsolve(sm, k + 1, x, false);  // coef1 holds s for the update pass
       }
       break;
     }
