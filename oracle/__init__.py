@@ -31,18 +31,44 @@ DCGS2_GUARD_GE3 = 1 << 4
 OK, EINVAL, EBREAKDOWN, ESTATE = 0, -1, -3, -4
 
 
+OMP_LIB_PATH = os.path.join(HERE, "liboracle_omp.so")
+
+
 def build(force: bool = True) -> str:
-    """Compile ``aa_oracle.c`` into ``liboracle.so`` with gcc (FP64, no contraction)."""
-    if force or not os.path.exists(LIB_PATH):
-        tmp = LIB_PATH + ".tmp"
-        subprocess.check_call([
-            "gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-            "-fPIC", "-shared", "-Wall", "-o", tmp, SRC_PATH, "-lm"])
-        os.replace(tmp, LIB_PATH)
+    """Compile ``aa_oracle.c`` into ``liboracle.so`` with gcc (FP64, no
+    contraction), and the same source with OpenMP into ``liboracle_omp.so``
+    (the CPU baseline: fixed row blocks, so the results are bitwise those of
+    the single-threaded build for any thread count)."""
+    for path, extra in ((LIB_PATH, []), (OMP_LIB_PATH, ["-fopenmp"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.check_call([
+                "gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                "-fPIC", "-shared", "-Wall", *extra, "-o", tmp, SRC_PATH, "-lm"])
+            os.replace(tmp, path)
     return LIB_PATH
 
 
+def use_openmp(threads: int) -> int:
+    """Switch this process to the OpenMP build with ``threads`` threads (the
+    CPU baseline); returns the thread count in effect."""
+    global _lib, _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(OMP_LIB_PATH):
+            build(force=False)
+        saved, real = _lib, LIB_PATH
+        try:
+            _lib = None
+            globals()["LIB_PATH"] = OMP_LIB_PATH
+            _lib_omp = lib()
+        finally:
+            globals()["LIB_PATH"] = real
+    _lib = _lib_omp
+    return int(_lib.or_set_threads(int(threads)))
+
+
 _lib = None
+_lib_omp = None
 
 
 def lib():
@@ -55,6 +81,7 @@ def lib():
         L.or_qr_add.argtypes = [C.POINTER(_QR), C.c_int, C.c_uint, P]
         L.or_qr_delete.argtypes = [C.POINTER(_QR), C.c_int, C.c_uint]
         L.or_qr_flush.argtypes = [C.POINTER(_QR), C.c_int]
+        L.or_set_threads.argtypes = [C.c_int]
         L.or_qr_rhs.argtypes = [C.POINTER(_QR), P, P]
         L.or_qr_rhs.restype = None
         L.or_backsolve.argtypes = [C.c_int, C.c_int, P, P, P]

@@ -18,7 +18,12 @@
  * Arithmetic: IEEE FP64, round to nearest, compiled with -ffp-contract=off so
  * no multiply-add is fused.  Dot products and norms use Neumaier-compensated
  * summation, so the oracle is at least as accurate as any GPU summation order.
- * No blocking, fusion or reordering beyond what the algorithms state.
+ * No fusion or reordering beyond what the algorithms state.  A dot product
+ * sums fixed blocks of OR_BLOCK rows (each compensated), then the block
+ * results in block order (compensated again): the same source built with
+ * OpenMP (-fopenmp, the CPU baseline) runs the blocks and the elementwise row
+ * loops on several threads and gives bitwise the same results as the
+ * single-threaded build, whatever the thread count.
  *
  * "Sync" counters: every global reduction the paper marks (Algs. 3-6 and the
  * ICWY refresh of T after QRDelete, Sec. 3.2) increments a counter, so tests
@@ -49,26 +54,84 @@ enum { OR_OK = 0, OR_EINVAL = -1, OR_EBREAKDOWN = -3, OR_ESTATE = -4 };
 /* vector primitives                                                   */
 /* ------------------------------------------------------------------ */
 
-/* x^T y with Neumaier's compensated summation of the rounded products. */
-static double dot(int64_t n, const double *x, const double *y) {
+#ifdef _OPENMP
+#include <omp.h>
+#define OR_PARALLEL_FOR _Pragma("omp parallel for schedule(static)")
+#else
+#define OR_PARALLEL_FOR
+#endif
+
+/* Rows per block of a dot product (the unit of work of a thread). */
+#define OR_BLOCK 65536
+
+/* Neumaier's compensated accumulation of p into (s, comp). */
+static inline void neumaier_add(double *s, double *comp, double p) {
+  double t = *s + p;
+  if (fabs(*s) >= fabs(p))
+    *comp += (*s - t) + p;
+  else
+    *comp += (p - t) + *s;
+  *s = t;
+}
+
+/* x^T y (or (x - y)^T (x - y) with diff) over rows [r0, r1), compensated. */
+static double block_dot(int64_t r0, int64_t r1, const double *x, const double *y, int diff) {
   double s = 0.0, comp = 0.0;
-  for (int64_t r = 0; r < n; ++r) {
-    double p = x[r] * y[r];
-    double t = s + p;
-    if (fabs(s) >= fabs(p))
-      comp += (s - t) + p;
-    else
-      comp += (p - t) + s;
-    s = t;
+  for (int64_t r = r0; r < r1; ++r) {
+    double p;
+    if (diff) {
+      double d = x[r] - y[r];
+      p = d * d;
+    } else {
+      p = x[r] * y[r];
+    }
+    neumaier_add(&s, &comp, p);
   }
   return s + comp;
+}
+
+/* Compensated sum of the block results in block order. */
+static double blocked_sum(int64_t n, const double *x, const double *y, int diff) {
+  int64_t nb = (n + OR_BLOCK - 1) / OR_BLOCK;
+  if (nb <= 1) return block_dot(0, n, x, y, diff);
+  double *part = (double *)malloc(sizeof(double) * (size_t)nb);
+  OR_PARALLEL_FOR
+  for (int64_t b = 0; b < nb; ++b) {
+    int64_t r1 = (b + 1) * OR_BLOCK;
+    part[b] = block_dot(b * OR_BLOCK, r1 < n ? r1 : n, x, y, diff);
+  }
+  double s = 0.0, comp = 0.0;
+  for (int64_t b = 0; b < nb; ++b) neumaier_add(&s, &comp, part[b]);
+  free(part);
+  return s + comp;
+}
+
+/* x^T y with Neumaier's compensated summation of the rounded products. */
+static double dot(int64_t n, const double *x, const double *y) { return blocked_sum(n, x, y, 0); }
+
+/* ||x - y||_2^2, compensated. */
+static double sqdist(int64_t n, const double *x, const double *y) {
+  return blocked_sum(n, x, y, 1);
 }
 
 static double nrm2(int64_t n, const double *x) { return sqrt(dot(n, x, x)); }
 
 /* y <- y - a x */
 static void axmy(int64_t n, double a, const double *x, double *y) {
+  OR_PARALLEL_FOR
   for (int64_t r = 0; r < n; ++r) y[r] = y[r] - a * x[r];
+}
+
+/* Threads of the OpenMP build (the CPU baseline); a no-op without OpenMP.
+ * Returns the thread count in effect. */
+int or_set_threads(int t) {
+#ifdef _OPENMP
+  if (t > 0) omp_set_num_threads(t);
+  return omp_get_max_threads();
+#else
+  (void)t;
+  return 1;
+#endif
 }
 
 /* ------------------------------------------------------------------ */
@@ -100,6 +163,7 @@ static int normalize_into(or_qr *s, double *v) {
   RM(s, k, k) = nv;
   if (!(nv > 0.0) || !isfinite(nv)) return OR_EBREAKDOWN;
   double *q = QCOL(s, k);
+  OR_PARALLEL_FOR
   for (int64_t r = 0; r < s->n; ++r) q[r] = v[r] / nv;
   s->k = k + 1;
   return OR_OK;
@@ -243,6 +307,7 @@ static int qr_add_dcgs2_lag(or_qr *s, double *v) {
   } else {
     double rho = sqrt(rho2);
     for (int j = 0; j < p; ++j) axmy(n, sc[j], QCOL(s, j), qp);
+    OR_PARALLEL_FOR
     for (int64_t r = 0; r < n; ++r) qp[r] = qp[r] / rho;
     double rpp = RM(s, p, p);
     for (int j = 0; j < p; ++j) RM(s, j, p) = RM(s, j, p) + rpp * sc[j];
@@ -264,6 +329,7 @@ static int qr_add_dcgs2_lag(or_qr *s, double *v) {
       axmy(n, rpk, qp, v);
       RM(s, k, k) = rkk;
       double *q = QCOL(s, k);
+      OR_PARALLEL_FOR
       for (int64_t r = 0; r < n; ++r) q[r] = v[r] / rkk;
       s->k = k + 1;
     }
@@ -296,6 +362,7 @@ int or_qr_flush(or_qr *s, int variant) {
   } else {
     double rho = sqrt(rho2);
     for (int j = 0; j < p; ++j) axmy(n, sc[j], QCOL(s, j), qp);
+    OR_PARALLEL_FOR
     for (int64_t r = 0; r < n; ++r) qp[r] = qp[r] / rho;
     double rpp = RM(s, p, p);
     for (int j = 0; j < p; ++j) RM(s, j, p) = RM(s, j, p) + rpp * sc[j];
@@ -392,6 +459,7 @@ int or_qr_delete(or_qr *s, int variant, unsigned flags) {
       gs[j] = sn;
     }
     double *qa = QCOL(s, j), *qb = QCOL(s, j + 1);
+    OR_PARALLEL_FOR
     for (int64_t r = 0; r < s->n; ++r) {
       double x = qa[r], y = qb[r];
       qa[r] = c * x + sn * y;
@@ -488,6 +556,7 @@ int or_aa_step(or_aa *a, const double *x, const double *g, double *x_next) {
   or_qr *s = &a->qr;
   int64_t n = s->n;
   if (a->i == 0) {
+    OR_PARALLEL_FOR
     for (int64_t r = 0; r < n; ++r) {
       a->f_prev[r] = g[r] - x[r];
       a->g_prev[r] = g[r];
@@ -495,12 +564,7 @@ int or_aa_step(or_aa *a, const double *x, const double *g, double *x_next) {
     }
     memcpy(a->f, a->f_prev, sizeof(double) * (size_t)n);
     a->res0_norm = a->res_norm = nrm2(n, a->f_prev);
-    a->step_norm = 0.0;
-    for (int64_t r = 0; r < n; ++r) {
-      double d = x_next[r] - x[r];
-      a->step_norm += d * d;
-    }
-    a->step_norm = sqrt(a->step_norm);
+    a->step_norm = sqrt(sqdist(n, x_next, x));
     a->m_i = 0;
     a->i = 1;
     return OR_OK;
@@ -511,6 +575,7 @@ int or_aa_step(or_aa *a, const double *x, const double *g, double *x_next) {
   int slot = (int)((i - 1) % m);
   double *df = a->dF + (int64_t)slot * s->ld;
   double *dg = a->dG + (int64_t)slot * s->ld;
+  OR_PARALLEL_FOR
   for (int64_t r = 0; r < n; ++r) {
     double fr = g[r] - x[r];
     df[r] = fr - a->f_prev[r];
@@ -534,6 +599,7 @@ int or_aa_step(or_aa *a, const double *x, const double *g, double *x_next) {
     a->status = st;
     return st;
   }
+  OR_PARALLEL_FOR
   for (int64_t r = 0; r < n; ++r) {
     double acc = g[r];
     for (int j = 0; j < m_i; ++j) {
@@ -542,12 +608,7 @@ int or_aa_step(or_aa *a, const double *x, const double *g, double *x_next) {
     }
     x_next[r] = acc;
   }
-  double st2 = 0.0;
-  for (int64_t r = 0; r < n; ++r) {
-    double d = x_next[r] - x[r];
-    st2 += d * d;
-  }
-  a->step_norm = sqrt(st2);
+  a->step_norm = sqrt(sqdist(n, x_next, x));
   a->m_i = m_i;
   a->i = i + 1;
   return OR_OK;
@@ -566,6 +627,7 @@ void or_G_stencil(int d, int64_t s, double h, double omega, double c,
   if (d >= 2) n *= s;
   if (d >= 3) n *= s;
   double ih2 = 1.0 / (h * h);
+  OR_PARALLEL_FOR
   for (int64_t p = 0; p < n; ++p) {
     int64_t ix = p % s, iy = (p / s) % s, iz = p / (s * s);
     double nb = 0.0;
@@ -590,6 +652,7 @@ void or_laplacian(int d, int64_t s, double h, const double *u, double *y) {
   if (d >= 2) n *= s;
   if (d >= 3) n *= s;
   double ih2 = 1.0 / (h * h);
+  OR_PARALLEL_FOR
   for (int64_t p = 0; p < n; ++p) {
     int64_t ix = p % s, iy = (p / s) % s, iz = p / (s * s);
     double nb = 0.0;
