@@ -1,25 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the Anderson-acceleration hot path on one MI355X.
 
-Workload (the 3D nonlinear fixed-point problem): G(u) = u - omega (A u + u^3 - f)
-on a 256^3 Dirichlet grid (n = 16,777,216), f ~ U[0, 1] (seed 2), u_0 = 0,
-window m = 20, FP64.  A step is one full recycle iteration of Alg. 1: one
-evaluation of G (HIP stencil kernel) and one ``aa_step`` -- history
-formation, QRDelete by Givens rotations, QRAdd of Delta f_{i-1} by the chosen
-variant, R gamma = Q^T f_i and the x update.  The window is filled (m + 1
-untimed start-up iterations) before the warmup, so every timed step deletes
-and adds a column.
+Headline (the metric: QRAdd GB/s as a fraction of HBM peak): one QRAdd of a
+Gaussian column v into a basis of k = 19 orthonormal columns (the add into a
+20-column window) at n = 2^26, FP64, by the chosen variant (default ICWY,
+Alg. 4).  A "step" is one such add: W untimed and K timed adds, each followed
+by an untimed QRDelete that restores k.  Every add is bracketed by its own
+pair of HIP events on the context's stream with the library's per-launch
+profiling off, so its time is its span on the GPU (kernels and the gaps
+between them).  value = algorithmic bytes of the add / median add time, where
+every n-vector a kernel must read or write counts 8 n bytes once (ICWY:
+(2k + 5) vectors; the library accounts this per launch).  The roofline object
+names the add's dominant kernel, timed per launch by events in a separate
+profiled pass.
 
-value = algorithmic HBM bytes of one step / time of one step, in GB/s, where
-every n-vector a kernel must read or write counts 8 n bytes once (the library
-accounts this per launch from its column counts; the stencil counts 3
-vectors).  The roofline object reports the kernel kind with the largest
-share of the step time, timed by HIP events that the library records around
-each launch on its stream during the timed steps.
+Also measured: the QRAdd / QRDelete table for every variant (n = 2^24 with
+k = m - 1, n = 2^26 with k = 1 .. 64; 10 reps, median and best), the
+bandwidth ceilings of plain access patterns with the passes' tiles and loads
+(aa_bandwidth_probe), the 3D nonlinear AA recycle iteration (G(u) = u -
+omega (A u + u^3 - f) on 256^3, window m = 20) per variant with its loss of
+orthogonality, the pass fusions, the window sweep, graph replay at mid
+sizes, the 1D Poisson solves, and the batched / learned-guarded /
+one-at-a-time comparison on the 4096-instance 2D table.
 
-The CPU baseline is the FP64 oracle (single thread) on a bounded sample of the
-same configuration: a 128^3 grid, same m and variant, 3 recycle iterations
-timed after filling the window; same byte model.
+The CPU baseline is the oracle (its OpenMP build, bitwise the serial results)
+on a bounded sample of the headline: the same add at n = 2^22, on one and on
+every host core.
 """
 from __future__ import annotations
 
@@ -38,7 +44,8 @@ VARIANTS = ["mgs", "cgs2", "dcgs2", "icwy"]
 PROFILE_JSON = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
-def run_variant(prob, m, variant, steps, warmup, grid=None, profile=True, flags=0):
+def run_variant(prob, m, variant, steps, warmup, grid=None, profile=True, flags=0,
+                keep_ctx=False):
     import torch
     from paper_2110_09667_amd import aa
 
@@ -96,7 +103,10 @@ def run_variant(prob, m, variant, steps, warmup, grid=None, profile=True, flags=
                         "gbs": (v[2] / v[0] / 1e6) if v[0] > 0 else None}
                     for k, v in prof.items() if v[1] > 0},
     }
-    ctx.close()
+    if keep_ctx:
+        out["ctx"] = ctx  # the caller closes it
+    else:
+        ctx.close()
     del x, g, f_d
     torch.cuda.empty_cache()
     return out
@@ -145,26 +155,30 @@ def graph_replay(sizes=(32, 48, 64, 96, 128), m=20, variant="icwy", steps=40):
     return out
 
 
-def qr_micro(n, ks, variant, reps=3):
+def qr_micro(n, ks, variant, flags=0, reps=10, busy_reps=3, warmup=1):
     """QRAdd / QRDelete on their own (the standalone microbenchmark): a basis
     of k orthonormal columns (seeded Gaussian columns added one by one), then
-    ``reps`` cycles of [QRAdd of a Gaussian v; QRDelete], which keeps k fixed.
-    Each call is timed with events on the context's stream; its algorithmic
-    bytes come from the library's per-launch accounting.  Returns
-    {k: {"add_us", "add_gbs", "delete_us", "delete_gbs"}} (medians)."""
+    ``warmup`` untimed and ``reps`` timed cycles of [QRAdd of a Gaussian v;
+    QRDelete], which keeps k fixed.  Timing runs with the library's
+    per-launch profiling off: a pair of events on the context's stream
+    brackets each add (and, separately, each delete), so a time is the add's
+    span on the GPU (its kernels and the gaps between them).  Then
+    ``busy_reps`` more cycles with per-launch profiling give the add's
+    algorithmic bytes (the library's accounting), its busy time (sum of its
+    kernels' event-timed durations) and its dominant kernel.  Returns
+    {k: {...}} with minima and medians."""
+    import numpy as np
     import torch
     from paper_2110_09667_amd import aa
     import aa_workloads as W
 
     dev = torch.device("cuda:0")
     kmax = max(ks)
-    ctx = aa.AAContext(n, kmax + 1, variant, flags=aa.QR_ONLY)
+    ctx = aa.AAContext(n, kmax + 1, variant, flags=flags | aa.QR_ONLY)
     col = torch.empty(n, dtype=torch.float64, device=dev)
     v = torch.empty(n, dtype=torch.float64, device=dev)
     aa.aa_fill_normal(v, W.SEED_QR_V, 0)
     stream = torch.cuda.current_stream(dev)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    ctx.profile(True)
     out = {}
     j = 0
     for k in sorted(ks):
@@ -172,30 +186,92 @@ def qr_micro(n, ks, variant, reps=3):
             aa.aa_fill_normal(col, W.SEED_QR_Q, j)
             ctx.qr_add(col)
             j += 1
-        adds, dels = [], []
-        for _ in range(reps):
-            torch.cuda.synchronize(dev)
-            aa.aa_profile_reset(ctx.ctx)
-            ev[0].record(stream)
+        for _ in range(warmup):
             ctx.qr_add(v)
-            ev[1].record(stream)
-            torch.cuda.synchronize(dev)
-            b_add = sum(b for (_, _, b) in ctx.profile_read().values())
-            aa.aa_profile_reset(ctx.ctx)
-            ev[1].record(stream)
             ctx.qr_delete()
-            ev[2].record(stream)
-            torch.cuda.synchronize(dev)
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
+        torch.cuda.synchronize(dev)
+        for r in range(reps):
+            ev[r][0].record(stream)
+            ctx.qr_add(v)
+            ev[r][1].record(stream)
+            ev[r][2].record(stream)
+            ctx.qr_delete()
+            ev[r][3].record(stream)
+        torch.cuda.synchronize(dev)
+        t_add = np.array([e[0].elapsed_time(e[1]) for e in ev])
+        t_del = np.array([e[2].elapsed_time(e[3]) for e in ev])
+        # per-launch profiling: bytes, busy time, per-kernel breakdown
+        ctx.profile(True)
+        busy, kerns, b_add, b_del = [], {}, 0.0, 0.0
+        for _ in range(busy_reps):
+            aa.aa_profile_reset(ctx.ctx)
+            ctx.qr_add(v)
+            prof = ctx.profile_read()
+            busy.append(sum(ms for (ms, _, _) in prof.values()))
+            b_add = sum(b for (_, _, b) in prof.values())
+            for kind, (ms, la, by) in prof.items():
+                if la:
+                    kk = kerns.setdefault(kind, [0.0, 0, 0.0])
+                    kk[0] += ms
+                    kk[1] += la
+                    kk[2] += by
+            aa.aa_profile_reset(ctx.ctx)
+            ctx.qr_delete()
             b_del = sum(b for (_, _, b) in ctx.profile_read().values())
-            adds.append((ev[0].elapsed_time(ev[1]), b_add))
-            dels.append((ev[1].elapsed_time(ev[2]), b_del))
+        ctx.profile(False)
         if ctx.info().status != 0:
             raise RuntimeError(f"qr_micro {variant} k={k}: status {ctx.info().status}")
-        (ta, ba), (td, bd) = sorted(adds)[reps // 2], sorted(dels)[reps // 2]
-        out[k] = {"add_us": 1e3 * ta, "add_gbs": ba / ta / 1e6,
-                  "delete_us": 1e3 * td, "delete_gbs": (bd / td / 1e6) if td > 0 else None}
+        stream_kinds = {kd: d for kd, d in kerns.items() if d[2] > 0}
+        dom = max(stream_kinds, key=lambda kd: stream_kinds[kd][0]) if stream_kinds else None
+        med_a, min_a = float(np.median(t_add)), float(t_add.min())
+        med_d = float(np.median(t_del))
+        out[k] = {"add_bytes": b_add,
+                  "add_us_median": 1e3 * med_a, "add_us_min": 1e3 * min_a,
+                  "add_gbs": b_add / med_a / 1e6, "add_gbs_best": b_add / min_a / 1e6,
+                  "add_busy_us": 1e3 * float(np.median(busy)),
+                  "add_busy_gbs": b_add / float(np.median(busy)) / 1e6,
+                  "delete_us_median": 1e3 * med_d,
+                  "delete_gbs": (b_del / med_d / 1e6) if med_d > 0 else None,
+                  "reps": reps,
+                  "dominant_kernel": dom,
+                  "kernels": {kd: {"us_per_launch": 1e3 * d[0] / d[1],
+                                   "bytes_per_launch": d[2] / d[1],
+                                   "gbs": (d[2] / d[0] / 1e6) if d[0] > 0 and d[2] > 0 else None}
+                              for kd, d in kerns.items()}}
     ctx.close()
     del col, v
+    torch.cuda.empty_cache()
+    return out
+
+
+def ceilings(n=1 << 26, reps=10):
+    """Sustained bandwidth of plain access patterns with the passes' tiles,
+    loads and launch shape (aa_bandwidth_probe): read streams (1, 4, 8
+    vectors), copy (1 read, 1 write), the MGS update's 3 reads + 1 write and
+    8 reads + 1 write; GB/s of the bytes read and written, best and median
+    of ``reps`` launches."""
+    import numpy as np
+    import torch
+    from paper_2110_09667_amd import aa
+    ld = n
+    src = torch.ones(8 * ld, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty(2 * ld, dtype=torch.float64, device="cuda:0")
+    sink = torch.empty(4096, dtype=torch.float64, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {}
+    for (rd, wr) in ((1, 0), (4, 0), (8, 0), (1, 1), (3, 1), (8, 1)):
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(reps + 1)]
+        for r in range(reps + 1):
+            ev[r][0].record(stream)
+            aa.aa_bandwidth_probe(rd, wr, src, ld, dst, n, sink)
+            ev[r][1].record(stream)
+        torch.cuda.synchronize()
+        t = np.array([e[0].elapsed_time(e[1]) for e in ev[1:]])
+        byt = 8.0 * n * (rd + wr)
+        out[f"{rd}r{wr}w"] = {"gbs_best": round(byt / t.min() / 1e6, 1),
+                              "gbs_median": round(byt / float(np.median(t)) / 1e6, 1)}
+    del src, dst, sink
     torch.cuda.empty_cache()
     return out
 
@@ -529,52 +605,74 @@ class Problem3D:
         self.omega = 0.9 / W.laplacian_lambda_max(3, s)
 
 
-def cpu_baseline(m, variant, s=128, timed_steps=3):
+def cpu_baseline(n=1 << 22, k=19, variant="icwy", reps=5):
+    """The oracle (its OpenMP build: fixed row blocks, bitwise the serial
+    results) on a bounded sample of the headline measurement: QRAdds of a
+    Gaussian column into a k-column basis at n = 2^22 (the GPU measures
+    n = 2^26), each followed by an untimed QRDelete, median of ``reps`` at 1
+    thread and at every host core; GB/s with the same byte model.  Also the
+    1D Poisson solves (1 thread)."""
     import numpy as np
 
     import aa_workloads as W
     import oracle as O
-    if not os.path.exists(O.LIB_PATH):
-        O.build()
-    prob = W.nonlinear3d(s=s)
-    n = prob.n
-    st = O.AA(n, m, variant)
-    x = np.zeros(n)
-    for _ in range(m + 1):
-        x = st.step(x, O.G_stencil(prob, x))
-    t0 = time.perf_counter()
-    for _ in range(timed_steps):
-        x = st.step(x, O.G_stencil(prob, x))
-    dt = time.perf_counter() - t0
+    allc = len(os.sched_getaffinity(0))
+    O.use_openmp(allc)
+    q = O.QR(n, k + 1, variant)
+    for j in range(k):
+        q.add(W.normal(W.SEED_QR_Q, j, n))
+    v = W.normal(W.SEED_QR_V, 0, n)
     u = 8.0 * n
-    k = m - 1
-    add = {"mgs": 4 * k + 3, "cgs2": 3 * k + 6, "dcgs2": 2 * k + (6 if k >= 3 else 5),
-           "icwy": 2 * k + 5}[variant]
-    vecs = 3 + 8 + (2 * m - 1) + add + 2 + (m + 1) + (m + 3)
-    # the 1D Poisson solve (n = 4096, m = 5, to 1e-8 or 300 iterations) per variant
+    vecs = {"mgs": 4 * k + 3, "cgs2": 3 * k + 6, "dcgs2": 2 * k + 6, "icwy": 2 * k + 5,
+            "dcgs2_lag": 2 * k + 4}[variant]
+    res = {}
+    for threads in (1, allc):
+        used = O.use_openmp(threads)
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            assert q.add(v) == O.OK
+            ts.append(time.perf_counter() - t0)
+            assert q.delete() == O.OK
+        dt = float(np.median(ts))
+        res[threads] = (vecs * u / dt / 1e9, dt, used)
+    O.use_openmp(1)
     p1 = W.poisson1d()
     poisson = {}
-    for v in VARIANTS:
+    for vv in VARIANTS:
         t1 = time.perf_counter()
-        _, _, res = O.run_aa(lambda z: O.G_stencil(p1, z), np.zeros(p1.n), 5, v, 300, tol=1e-8,
-                             record=False)
-        poisson[v] = {"iterations": len(res), "ms": round(1e3 * (time.perf_counter() - t1), 3)}
-    return {"value": vecs * u * timed_steps / dt / 1e9, "unit": "GB/s", "cores": 1,
-            "kind": "oracle", "poisson1d_to_1e-8": poisson,
-            "sample": (f"FP64 C oracle, 1 thread: {timed_steps} recycle iterations of the same "
-                       f"configuration (m={m}, {variant}) on a {s}^3 grid (n={n}) after "
-                       f"filling the window; {dt:.2f} s timed")}
+        _, _, r = O.run_aa(lambda z: O.G_stencil(p1, z), np.zeros(p1.n), 5, vv, 300, tol=1e-8,
+                           record=False)
+        poisson[vv] = {"iterations": len(r), "ms": round(1e3 * (time.perf_counter() - t1), 3)}
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    gb_all, dt_all, used_all = res[allc]
+    gb_1, dt_1, _ = res[1]
+    return {"value": round(gb_all, 3), "unit": "GB/s", "cores": used_all, "kind": "oracle",
+            "one_core_value": round(gb_1, 3), "nproc": os.cpu_count(), "cpu_model": model,
+            "poisson1d_to_1e-8_one_core": poisson,
+            "sample": (f"FP64 C oracle (OpenMP build, fixed row blocks): one {variant} QRAdd "
+                       f"into a {k}-column basis at n = {n} (the GPU line is n = 2^26), "
+                       f"median of {reps}: {dt_all:.2f} s on {used_all} threads, {dt_1:.2f} s "
+                       f"on 1")}
 
 
-def load_traffic(kind, variant, m):
+def load_traffic(workload, kind):
     """HBM bytes per launch measured with rocprofv3 counters, if a summary for
-    this kernel and configuration is committed and still current."""
+    this kernel and workload is committed and its kernel sources have not
+    changed since."""
     try:
         with open(PROFILE_JSON) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    key = f"{kind}/{variant}/m{m}"
+    key = f"{workload}/{kind}"
     ent = d.get(key)
     if not ent or ent.get("source_hash") != source_hash():
         return None
@@ -591,23 +689,48 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
+QR_VARIANTS = [("mgs", 0), ("cgs2", 0), ("dcgs2", 0), ("icwy", 0), ("dcgs2_lag", 0),
+               ("icwy_T_transform", 1 << 2)]
+
+
+def variant_name(label):
+    return "icwy" if label == "icwy_T_transform" else label
+
+
+def orthogonality(ctx, m):
+    """||I - Q^T Q||_F of the context's basis (torch FP64 products, column by
+    column block) and kappa_2(R), for the bounds of Sec. 2.2."""
+    import numpy as np
+    import torch
+    Q = ctx.basis(m).contiguous()
+    G = torch.empty((m, m), dtype=torch.float64, device=Q.device)
+    for a in range(m):
+        G[a] = Q[:, a] @ Q
+    orth = torch.linalg.norm(torch.eye(m, dtype=torch.float64, device=Q.device) - G).item()
+    R = ctx.get_qr()[0]
+    return orth, float(np.linalg.cond(R))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed QRAdds of the headline measurement (and AA steps of the "
+                         "3D workload)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--variant", default="icwy", choices=VARIANTS)
-    ap.add_argument("--m", type=int, default=20)
-    ap.add_argument("--s", type=int, default=256, help="grid points per side")
+    ap.add_argument("--k", type=int, default=19, help="columns before the headline QRAdd")
+    ap.add_argument("--m", type=int, default=20, help="window of the 3D AA step")
+    ap.add_argument("--s", type=int, default=256, help="grid points per side (3D AA step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-other-variants", action="store_true")
     ap.add_argument("--grid", type=int, nargs=2, default=None,
                     help="max workgroups: streaming passes, Gram pass")
     ap.add_argument("--no-qr-micro", action="store_true",
-                    help="skip the standalone QRAdd/QRDelete measurements")
+                    help="skip the QRAdd/QRDelete table (the headline add still runs)")
     ap.add_argument("--rhs", choices=["separate", "fused"], default="separate",
                     help="R gamma = Q^T f_i as its own pass (as Alg. 2 writes it) or folded "
-                         "into the QRAdd passes (AA_FUSE_RHS)")
+                         "into the QRAdd passes (AA_FUSE_RHS) in the 3D AA steps")
     ap.add_argument("--batch-passes", choices=["separate", "fused"], default="fused",
                     help="batched runs with the paper's separate passes or with the RHS folded "
                          "into QRAdd and QRDelete fused with its first pass")
@@ -621,13 +744,19 @@ def main():
     ap.add_argument("--single-sample", type=int, default=64,
                     help="instances run one at a time for the comparison")
     ap.add_argument("--qr-micro-only", action="store_true",
-                    help="only the QRAdd / QRDelete microbenchmark at n = 2^26, k = 1 .. 64 "
-                         "(one JSON line per variant; for kernel traces)")
+                    help="only the QRAdd / QRDelete table at n = 2^26 (one JSON line per "
+                         "variant; for kernel traces)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline QRAdd (for kernel traces and counters)")
+    ap.add_argument("--ceilings-only", action="store_true",
+                    help="only the bandwidth probes (read streams, copy, 3 reads + 1 write)")
     ap.add_argument("--c2-to-tol", action="store_true",
                     help="only the 3D nonlinear workload (256^3) solved to 1e-8 per variant and "
                          "m in {5, 10, 20, 50} (long: several minutes; one JSON line each)")
     ap.add_argument("--c2-cap", type=int, default=20000,
                     help="iteration cap of --c2-to-tol")
+    ap.add_argument("--c2-only", action="store_true",
+                    help="only the 3D AA step of --variant and --m (for kernel traces)")
     ap.add_argument("--poisson-only", action="store_true",
                     help="only the 1D Poisson time-to-tolerance measurement (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -652,7 +781,6 @@ def main():
         sys.exit(2)
 
     import torch
-    import aa_workloads as W
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
@@ -666,15 +794,19 @@ def main():
         for v in VARIANTS:
             print(json.dumps({v: poisson1d_to_tolerance(v)}), flush=True)
         return
-
-    if args.qr_micro_only:
-        for v in VARIANTS:
-            ks = [min(k, 63) if v == "icwy" else k for k in (1, 2, 4, 8, 16, 32, 64)]
-            r = qr_micro(1 << 26, ks, v)
-            print(json.dumps({"variant": v, "n": 1 << 26,
-                              **{f"k={k}": d for k, d in r.items()}}), flush=True)
+    if args.ceilings_only:
+        print(json.dumps({"ceilings_n2e26": ceilings()}), flush=True)
         return
-
+    if args.qr_micro_only:
+        for label, fl in QR_VARIANTS:
+            v = variant_name(label)
+            ks = [min(k, 63) if v == "icwy" else k for k in (1, 2, 4, 8, 16, 32, 64)]
+            r = qr_micro(1 << 26, ks, v, fl)
+            print(json.dumps({"variant": label, "n": 1 << 26,
+                              **{f"k={k}": {kk: d[kk] for kk in ("add_us_median", "add_gbs",
+                                                                  "add_busy_gbs", "delete_gbs")}
+                                 for k, d in r.items()}}), flush=True)
+        return
     if args.c2_to_tol:
         prob = Problem3D(args.s)
         for mm in (5, 10, 20, 50):
@@ -683,85 +815,109 @@ def main():
                 print(json.dumps({"workload": f"3D nonlinear {args.s}^3 to 1e-8", "m": mm,
                                   "variant": v, **r}), flush=True)
         return
+    if args.c2_only:
+        prob = Problem3D(args.s)
+        r = run_variant(prob, args.m, args.variant, args.steps, args.warmup, args.grid,
+                        flags=aa.FUSE_RHS if args.rhs == "fused" else 0)
+        print(json.dumps({"variant": args.variant, "m": args.m, "ms_per_step": r["ms_per_step"],
+                          "gbs": r["gbs"]}), flush=True)
+        return
 
-    prob = Problem3D(args.s)
-    print(f"# workload: 3D nonlinear, s={args.s}, n={prob.n}, m={args.m}", file=sys.stderr,
-          flush=True)
-    flags = aa.FUSE_RHS if args.rhs == "fused" else 0
-    main_res = run_variant(prob, args.m, args.variant, args.steps, args.warmup, args.grid,
-                           flags=flags)
-    print(f"# {args.variant}: {main_res['ms_per_step']:.3f} ms/step, "
-          f"{main_res['gbs']:.0f} GB/s", file=sys.stderr, flush=True)
-    others = {}
-    if not args.no_other_variants:
-        for v in VARIANTS:
-            if v == args.variant:
-                continue
-            r = run_variant(prob, args.m, v, max(5, args.steps // 2), 2, args.grid, flags=flags)
-            others[v] = r
-            print(f"# {v}: {r['ms_per_step']:.3f} ms/step, {r['gbs']:.0f} GB/s",
-                  file=sys.stderr, flush=True)
+    # ---- the headline: one QRAdd into a k-column basis at n = 2^26 ------------
+    n_head = 1 << 26
+    head = qr_micro(n_head, [args.k], args.variant, reps=args.steps, warmup=args.warmup)[args.k]
+    print(f"# headline QRAdd {args.variant} n=2^26 k={args.k}: {head['add_us_median']:.1f} us "
+          f"(min {head['add_us_min']:.1f}), {head['add_gbs']:.0f} GB/s "
+          f"({100 * head['add_gbs'] / HBM_PEAK_GBS:.1f} % of HBM peak); busy "
+          f"{head['add_busy_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
+    if args.headline_only:
+        print(json.dumps({"headline": head}), flush=True)
+        return
 
-    fused_rhs = {}
-    if not args.no_other_variants and args.rhs == "separate":
-        # the same steps with R gamma = Q^T f_i folded into the QRAdd passes
-        for v in VARIANTS:
-            r = run_variant(prob, args.m, v, max(5, args.steps // 2), 2, args.grid,
-                            profile=False, flags=aa.FUSE_RHS)
-            sep = main_res if v == args.variant else others[v]
-            fused_rhs[v] = {"ms_per_step": round(r["ms_per_step"], 4),
-                            "speedup_vs_separate": round(sep["ms_per_step"] / r["ms_per_step"], 3)}
-            print(f"# {v} with the RHS folded into QRAdd: {r['ms_per_step']:.3f} ms/step",
-                  file=sys.stderr, flush=True)
-            if v != "mgs":
-                # also merging QRDelete's pass with the QRAdd's first
-                r2 = run_variant(prob, args.m, v, max(5, args.steps // 2), 2, args.grid,
-                                 profile=False, flags=aa.FUSE_RHS | aa.FUSE_DELETE)
-                fused_rhs[v]["with_fused_delete"] = {
-                    "ms_per_step": round(r2["ms_per_step"], 4),
-                    "speedup_vs_separate": round(sep["ms_per_step"] / r2["ms_per_step"], 3)}
-                print(f"# {v} with the RHS folded and QRDelete fused with QRAdd: "
-                      f"{r2['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
-
-    m_sweep = {}
-    if not args.no_other_variants:
-        # the other windows of the 3D workload (m = 5, 10, 50), paper passes
-        for v in VARIANTS:
-            m_sweep[v] = {}
-            for mm in (5, 10, 50):
-                if mm == args.m:
-                    continue
-                r = run_variant(prob, mm, v, 5, 2, args.grid, flags=0)
-                m_sweep[v][f"m={mm}"] = {"ms_per_step": round(r["ms_per_step"], 4),
-                                         "gbs": round(r["gbs"], 1),
-                                         "pct_hbm_peak": round(100 * r["gbs"] / HBM_PEAK_GBS, 1)}
-            print(f"# {v} m sweep: " + ", ".join(f"{k} {d['ms_per_step']:.2f} ms "
-                                                  f"{d['gbs']:.0f} GB/s"
-                                                  for k, d in m_sweep[v].items()),
-                  file=sys.stderr, flush=True)
-
-    graphs = graph_replay() if not args.no_other_variants else {}
+    ceil = ceilings()
+    print("# ceilings: " + ", ".join(f"{k} {d['gbs_best']:.0f}" for k, d in ceil.items()),
+          file=sys.stderr, flush=True)
 
     qradd = {}
     if not args.no_qr_micro:
         # QRAdd / QRDelete alone: at the 3D workload's n with k = m - 1 (the
         # add that follows a delete in a full window, m = 5, 10, 20, 50), and
         # at n = 2^26 for k = 1..64
-        for label, n_q, ks in (("n=%d" % prob.n, prob.n, [4, 9, 19, 49]),
-                               ("n=%d" % (1 << 26), 1 << 26, [1, 2, 4, 8, 16, 32, 64])):
-            qradd[label] = {}
-            for v in VARIANTS:
+        for label_n, n_q, ks in (("n=%d" % (1 << 24), 1 << 24, [4, 9, 19, 49]),
+                                 ("n=%d" % n_head, n_head, [1, 2, 4, 8, 9, 16, 19, 32, 64])):
+            qradd[label_n] = {}
+            for label, fl in QR_VARIANTS:
+                v = variant_name(label)
                 # the ICWY window holds at most 64 columns: its largest add is k = 63
-                r = qr_micro(n_q, [min(k, 63) if v == "icwy" else k for k in ks], v)
-                qradd[label][v] = {f"k={k}": {"add_us": round(d["add_us"], 1),
-                                              "add_gbs": round(d["add_gbs"], 1),
-                                              "add_pct_hbm": round(100 * d["add_gbs"] / HBM_PEAK_GBS, 1),
-                                              "delete_us": round(d["delete_us"], 1),
-                                              "delete_gbs": (round(d["delete_gbs"], 1)
-                                                             if d["delete_gbs"] else None)}
-                                   for k, d in r.items()}
-                print(f"# qradd {label} {v}: " + ", ".join(
-                    f"k={k} {d['add_gbs']:.0f}" for k, d in r.items()), file=sys.stderr, flush=True)
+                r = qr_micro(n_q, [min(k, 63) if v == "icwy" else k for k in ks], v, fl)
+                qradd[label_n][label] = {
+                    f"k={k}": {"add_us_median": round(d["add_us_median"], 1),
+                               "add_us_min": round(d["add_us_min"], 1),
+                               "add_gbs": round(d["add_gbs"], 1),
+                               "add_gbs_best": round(d["add_gbs_best"], 1),
+                               "add_pct_hbm": round(100 * d["add_gbs"] / HBM_PEAK_GBS, 1),
+                               "add_busy_gbs": round(d["add_busy_gbs"], 1),
+                               "delete_us_median": round(d["delete_us_median"], 1),
+                               "delete_gbs": (round(d["delete_gbs"], 1)
+                                              if d["delete_gbs"] else None),
+                               "dominant_kernel": d["dominant_kernel"]}
+                    for k, d in r.items()}
+                print(f"# qradd {label_n} {label}: " + ", ".join(
+                    f"k={k} {d['add_gbs']:.0f}" for k, d in r.items()), file=sys.stderr,
+                    flush=True)
+
+    # ---- the 3D AA recycle iteration (C2) per variant --------------------------
+    prob = Problem3D(args.s)
+    c2_flags = aa.FUSE_RHS if args.rhs == "fused" else 0
+    c2 = {}
+    if not args.no_other_variants:
+        for label, fl in QR_VARIANTS:
+            v = variant_name(label)
+            r = run_variant(prob, args.m, v, max(5, args.steps // 2), 2, args.grid,
+                            flags=fl | c2_flags, keep_ctx=True)
+            orth, kap = orthogonality(r["ctx"], args.m)
+            r["ctx"].close()
+            c2[label] = {"ms_per_step": round(r["ms_per_step"], 4), "gbs": round(r["gbs"], 1),
+                         "pct_hbm_peak": round(100 * r["gbs"] / HBM_PEAK_GBS, 1),
+                         "orthogonality_loss": orth, "kappa_R": kap,
+                         "kernels": {kk: {"gbs": round(d["gbs"], 1) if d["gbs"] else None,
+                                          "us_per_step": round(1e3 * d["ms"] / r["steps"], 1)}
+                                     for kk, d in r["kernels"].items()}}
+            print(f"# c2 {label} m={args.m}: {r['ms_per_step']:.3f} ms/step, "
+                  f"{r['gbs']:.0f} GB/s, ||I-Q^TQ|| {orth:.1e} (kappa(R) {kap:.1e})",
+                  file=sys.stderr, flush=True)
+
+    fused = {}
+    if not args.no_other_variants:
+        # the same steps with R gamma = Q^T f_i folded into the QRAdd passes and
+        # QRDelete fused with the QRAdd's first pass (same method, fewer passes)
+        for v in ("cgs2", "dcgs2", "icwy"):
+            r2 = run_variant(prob, args.m, v, max(5, args.steps // 2), 2, args.grid,
+                             profile=False, flags=aa.FUSE_RHS | aa.FUSE_DELETE)
+            fused[v] = {"ms_per_step": round(r2["ms_per_step"], 4),
+                        "speedup_vs_separate": round(c2[v]["ms_per_step"] / r2["ms_per_step"], 3)}
+            print(f"# {v} with the RHS folded and QRDelete fused with QRAdd: "
+                  f"{r2['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+
+    m_sweep = {}
+    if not args.no_other_variants:
+        # the other windows of the 3D workload (m = 5, 10, 50), paper passes
+        for label, fl in QR_VARIANTS:
+            v = variant_name(label)
+            m_sweep[label] = {}
+            for mm in (5, 10, 50):
+                if mm == args.m:
+                    continue
+                r = run_variant(prob, mm, v, 5, 2, args.grid, flags=fl)
+                m_sweep[label][f"m={mm}"] = {"ms_per_step": round(r["ms_per_step"], 4),
+                                             "gbs": round(r["gbs"], 1),
+                                             "pct_hbm_peak": round(100 * r["gbs"] / HBM_PEAK_GBS, 1)}
+            print(f"# {label} m sweep: " + ", ".join(f"{k} {d['ms_per_step']:.2f} ms "
+                                                      f"{d['gbs']:.0f} GB/s"
+                                                      for k, d in m_sweep[label].items()),
+                  file=sys.stderr, flush=True)
+
+    graphs = graph_replay() if not args.no_other_variants else {}
 
     poisson = {}
     if not args.no_other_variants:
@@ -778,54 +934,65 @@ def main():
                                 fuse=(aa.FUSE_RHS | aa.FUSE_DELETE)
                                 if args.batch_passes == "fused" else 0)
 
-    kern = main_res["kernels"]
-    dom = max((k for k in kern if kern[k]["bytes"] > 0), key=lambda k: kern[k]["ms"])
-    achieved = kern[dom]["gbs"]
-    traffic = load_traffic(dom, args.variant, args.m)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+    # the roofline of the headline add's dominant kernel: algorithmic bytes per
+    # launch / its average launch duration (per-launch events on the
+    # context's stream)
+    dom = head["dominant_kernel"]
+    kd = head["kernels"][dom]
+    achieved = kd["gbs"]
+    traffic = load_traffic(f"qradd_{args.variant}_k{args.k}_n2e26", dom)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "launches": kern[dom]["launches"],
-                "algorithmic_bytes_per_launch": kern[dom]["bytes"] / kern[dom]["launches"]}
+                "algorithmic_bytes_per_launch": kd["bytes_per_launch"],
+                "us_per_launch": round(kd["us_per_launch"], 2),
+                "frac_of_measured_ceiling": round(
+                    achieved / max(ceil["8r0w"]["gbs_best"], ceil["8r1w"]["gbs_best"]), 4)}
 
     cpu = None
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(args.m, args.variant)
+        cpu = cpu_baseline(k=args.k, variant=args.variant)
 
-    per_variant = {args.variant: main_res, **others}
     line = {
         "metric": METRIC,
-        "value": main_res["gbs"],
+        "value": round(head["add_gbs"], 1),
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": main_res["ms_per_step"],
+        "ms_per_step": head["add_us_median"] / 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"AA recycle iteration, 3D nonlinear {args.s}^3 "
-                               f"(n={prob.n}), m={args.m}",
-                   "variant": args.variant, "n": prob.n, "m": args.m, "rhs": args.rhs,
+        "config": {"workload": f"QRAdd microbenchmark: {args.variant}, n = 2^26, k = {args.k} "
+                               f"(the add into a {args.k + 1}-column window), seeded Gaussian "
+                               f"columns orthonormalized by the library, v ~ N(0, 1)",
+                   "variant": args.variant, "n": n_head, "k": args.k,
                    "parallelism": "single GPU"},
-        "pct_hbm_peak": 100.0 * main_res["gbs"] / HBM_PEAK_GBS,
+        "pct_hbm_peak": round(100.0 * head["add_gbs"] / HBM_PEAK_GBS, 2),
+        "headline_add": {"us_median": round(head["add_us_median"], 1),
+                         "us_min": round(head["add_us_min"], 1),
+                         "gbs_median": round(head["add_gbs"], 1),
+                         "gbs_best": round(head["add_gbs_best"], 1),
+                         "busy_gbs": round(head["add_busy_gbs"], 1),
+                         "algorithmic_bytes": head["add_bytes"],
+                         "pct_of_measured_read_ceiling": round(
+                             100 * head["add_gbs"] / ceil["8r0w"]["gbs_best"], 1),
+                         "kernels": {kk: {a: round(b, 2) if isinstance(b, float) else b
+                                          for a, b in d.items()}
+                                     for kk, d in head["kernels"].items()}},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "poisson1d_to_1e-8": poisson,
-        "m_sweep": m_sweep,
-        "graph_replay_icwy_m20": graphs,
-        "fused_rhs": fused_rhs,
+        "ceilings_n2e26": ceil,
         "qradd": qradd,
+        "c2_step_256cubed": {"m": args.m, "rhs": args.rhs, "variants": c2,
+                             "with_fused_rhs_and_delete": fused, "m_sweep": m_sweep},
+        "poisson1d_to_1e-8": poisson,
+        "graph_replay_icwy_m20": graphs,
         "batched": batched,
-        "per_variant": {v: {"ms_per_step": r["ms_per_step"], "gbs": r["gbs"],
-                            "pct_hbm_peak": 100.0 * r["gbs"] / HBM_PEAK_GBS,
-                            "kernels": {k: {"gbs": round(d["gbs"], 1) if d["gbs"] else None,
-                                            "us_per_step": round(1e3 * d["ms"] / r["steps"], 1)}
-                                        for k, d in r["kernels"].items()}}
-                        for v, r in per_variant.items()},
     }
     print(json.dumps(line), flush=True)
 

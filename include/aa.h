@@ -434,6 +434,17 @@ aa_status aa_fill_uniform(double *d_out, int64_t n, uint64_t seed,
 aa_status aa_fill_normal(double *d_out, int64_t n, uint64_t seed,
                          uint64_t stream_id, uint64_t offset, void *stream);
 
+/* Measurement: the sustained HBM bandwidth of an access pattern, with the
+ * streaming passes' tiles, loads, stores and launch shape (at most 1024
+ * workgroups, one resident round).  Reads `reads` vectors of length n from
+ * d_src (vector j at d_src + j * ld) and writes `writes` vectors to d_dst
+ * (each the sum of the read ones); with writes == 0 every workgroup writes
+ * one partial sum to d_sink (at least 1024 doubles).  (reads, writes) in
+ * {(1,0), (4,0), (8,0), (1,1), (2,1), (3,1), (8,1), (1,2)}, else AA_EINVAL.
+ * Asynchronous on `stream`. */
+aa_status aa_bandwidth_probe(int reads, int writes, const double *d_src, int64_t ld,
+                             double *d_dst, int64_t n, double *d_sink, void *stream);
+
 /* Library version string. */
 const char *aa_version(void);
 

@@ -37,7 +37,7 @@ SYMBOLS = [
     "aa_mlp_workspace_size", "aa_mlp_init", "aa_mlp_reseed", "aa_mlp_set_params",
     "aa_mlp_get_params", "aa_mlp_get_grads", "aa_mlp_forward", "aa_mlp_backward",
     "aa_mlp_adam", "aa_mlp_destroy", "aa_batch_run_learned", "aa_batch_train",
-    "aa_batch_read_learning", "aa_qr_solve_noalloc",
+    "aa_batch_read_learning", "aa_qr_solve_noalloc", "aa_bandwidth_probe",
 ]
 
 BATCH_LEARNED = 1 << 9
@@ -100,6 +100,7 @@ def lib():
         "aa_qr_delete": [P],
         "aa_qr_solve": [P, P, P],
         "aa_qr_solve_noalloc": [P, I64, I64, I, P, I, P, P, P],
+        "aa_bandwidth_probe": [I, I, P, I64, P, I64, P, P],
         "aa_get_qr": [P, P, P, C.POINTER(C.c_int)],
         "aa_qr_basis": [P, C.POINTER(P), C.POINTER(I64)],
         "aa_qr_load": [P, I, P, I64, P, P],
@@ -200,6 +201,11 @@ def aa_qr_delete(ctx):
 
 def aa_qr_solve(ctx, f, gamma):
     _check(lib().aa_qr_solve(ctx, _ptr(f), _ptr(gamma)), "aa_qr_solve")
+
+
+def aa_bandwidth_probe(reads, writes, src, ld, dst, n, sink, stream=None):
+    _check(lib().aa_bandwidth_probe(reads, writes, _ptr(src), ld, _ptr(dst), n, _ptr(sink),
+                                    _stream(stream)), "aa_bandwidth_probe")
 
 
 def aa_qr_solve_noalloc(Q, ldq, n, k, R, ldr, f, gamma, stream=None):

@@ -967,6 +967,16 @@ aa_status aa_fill_normal(double* out, int64_t n, uint64_t seed, uint64_t stream_
   return hip_ok(launch_fill_normal(out, n, seed, stream_id, offset, (hipStream_t)stream));
 }
 
+aa_status aa_bandwidth_probe(int reads, int writes, const double* src, int64_t ld, double* dst,
+                             int64_t n, double* sink, void* stream) {
+  if (n < 1 || ld < n || !src || (writes > 0 && !dst) || (writes == 0 && !sink)) return AA_EINVAL;
+  int64_t g = (n + kTile - 1) / kTile;
+  const int grid = (int)(g > 1024 ? 1024 : g);
+  const hipError_t e =
+      launch_probe(reads, writes, src, ld, dst, n, sink, grid, (hipStream_t)stream);
+  return e == hipErrorInvalidValue ? AA_EINVAL : hip_ok(e);
+}
+
 const char* aa_version(void) { return "aa-mi355x 0.1 (gfx950, fp64)"; }
 
 }  // extern "C"

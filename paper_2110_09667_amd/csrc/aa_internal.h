@@ -240,6 +240,9 @@ hipError_t launch_scale(const ScaleArgs&, const Small&, hipStream_t);
 hipError_t launch_history(const HistArgs&, const Small&, const Tail&, int grid, hipStream_t);
 hipError_t launch_xupdate(const XupdArgs&, const Small&, const Tail&, int grid, hipStream_t);
 hipError_t launch_init_small(const Small&, hipStream_t);
+// (reads, writes) in {(1,0), (4,0), (8,0), (1,1), (2,1), (3,1), (8,1), (1,2)}
+hipError_t launch_probe(int reads, int writes, const double* src, int64_t ld, double* dst,
+                        int64_t n, double* sink, int grid, hipStream_t);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t);
 
 // problems and generators (aa_problems.hip)

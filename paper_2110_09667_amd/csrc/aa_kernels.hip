@@ -298,6 +298,50 @@ __global__ void k_copy(double* dst, const double* src, int64_t n) {
     dst[i] = src[i];
 }
 
+// Bandwidth probe with the passes' access pattern (same tiles, 16-byte
+// non-temporal loads of full tiles, plain stores as in the update pass):
+// read RD vectors of length n (leading dimension ld), write WR vectors, each
+// written vector the sum of the read ones; with no write, each workgroup
+// writes one partial sum to sink so the loads cannot be dropped.
+template <int RD, int WR>
+__global__ __launch_bounds__(kWG) void k_probe(const double* src, int64_t ld, double* dst,
+                                               int64_t n, double* sink) {
+  double acc = 0.0;
+  for_tiles(n, blockIdx.x, gridDim.x, [&](int64_t b2, auto full) {
+    constexpr bool F = decltype(full)::value;
+    double2 v[RD][kPairs];
+#pragma unroll
+    for (int j = 0; j < RD; ++j) ld2<F>(v[j], src + (int64_t)j * ld, b2, n);
+    double2 o[kPairs];
+    zero2(o);
+#pragma unroll
+    for (int j = 0; j < RD; ++j)
+#pragma unroll
+      for (int i = 0; i < kPairs; ++i) {
+        o[i].x += v[j][i].x;
+        o[i].y += v[j][i].y;
+      }
+    if constexpr (WR > 0) {
+#pragma unroll
+      for (int w = 0; w < WR; ++w) st2<F>(o, dst + (int64_t)w * ld, b2, n);
+    } else {
+#pragma unroll
+      for (int i = 0; i < kPairs; ++i) acc += o[i].x + o[i].y;
+    }
+  });
+  if constexpr (WR == 0) {
+    __shared__ double s_w[kWaves];
+    const double t = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double u = 0.0;
+      for (int w = 0; w < kWaves; ++w) u += s_w[w];
+      sink[blockIdx.x] = u;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -545,6 +589,32 @@ hipError_t launch_xupdate(const XupdArgs& a, const Small& sm, const Tail& t, int
   grid = clamp_resident(grid, reinterpret_cast<const void*>(&k_xupdate), kWG, 0);
   hipLaunchKernelGGL(k_xupdate, dim3(grid), dim3(kWG), 0, st, a, sm);
   return launch_finalize(sm, t, 1, grid, st);
+}
+
+hipError_t launch_probe(int reads, int writes, const double* src, int64_t ld, double* dst,
+                        int64_t n, double* sink, int grid, hipStream_t st) {
+  (void)hipGetLastError();  // drop a stale error left by an earlier call
+  auto go = [&](const void* kern, auto launch) {
+    grid = clamp_resident(grid, kern, kWG, 0);
+    launch(grid);
+  };
+#define AA_PROBE(RD, WR)                                                              \
+  if (reads == RD && writes == WR) {                                                   \
+    go(reinterpret_cast<const void*>(&k_probe<RD, WR>), [&](int g) {                   \
+      hipLaunchKernelGGL((k_probe<RD, WR>), dim3(g), dim3(kWG), 0, st, src, ld, dst, n, sink); \
+    });                                                                                \
+    return hipGetLastError();                                                          \
+  }
+  AA_PROBE(1, 0)
+  AA_PROBE(4, 0)
+  AA_PROBE(8, 0)
+  AA_PROBE(1, 1)
+  AA_PROBE(2, 1)
+  AA_PROBE(3, 1)
+  AA_PROBE(8, 1)
+  AA_PROBE(1, 2)
+#undef AA_PROBE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_init_small(const Small& sm, hipStream_t st) {
