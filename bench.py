@@ -159,7 +159,9 @@ def qr_micro(n, ks, variant, flags=0, reps=10, busy_reps=3, warmup=1):
     """QRAdd / QRDelete on their own (the standalone microbenchmark): a basis
     of k orthonormal columns (seeded Gaussian columns added one by one), then
     ``warmup`` untimed and ``reps`` timed cycles of [QRAdd of a Gaussian v;
-    QRDelete], which keeps k fixed.  Timing runs with the library's
+    QRDelete], which keeps k fixed; every cycle adds a fresh v (generated
+    before the add's events: re-adding the same v after a delete that kept it
+    would add a vector already in the span).  Timing runs with the library's
     per-launch profiling off: a pair of events on the context's stream
     brackets each add (and, separately, each delete), so a time is the add's
     span on the GPU (its kernels and the gaps between them).  Then
@@ -186,12 +188,21 @@ def qr_micro(n, ks, variant, flags=0, reps=10, busy_reps=3, warmup=1):
             aa.aa_fill_normal(col, W.SEED_QR_Q, j)
             ctx.qr_add(col)
             j += 1
+        cyc = 0
+
+        def fresh_v():
+            nonlocal cyc
+            aa.aa_fill_normal(v, W.SEED_QR_V, 1000 * k + cyc)
+            cyc += 1
+
         for _ in range(warmup):
+            fresh_v()
             ctx.qr_add(v)
             ctx.qr_delete()
         ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
         torch.cuda.synchronize(dev)
         for r in range(reps):
+            fresh_v()
             ev[r][0].record(stream)
             ctx.qr_add(v)
             ev[r][1].record(stream)
@@ -205,6 +216,7 @@ def qr_micro(n, ks, variant, flags=0, reps=10, busy_reps=3, warmup=1):
         ctx.profile(True)
         busy, kerns, b_add, b_del = [], {}, 0.0, 0.0
         for _ in range(busy_reps):
+            fresh_v()
             aa.aa_profile_reset(ctx.ctx)
             ctx.qr_add(v)
             prof = ctx.profile_read()
@@ -254,7 +266,11 @@ def ceilings(n=1 << 26, reps=10):
     import numpy as np
     import torch
     from paper_2110_09667_amd import aa
-    ld = n
+    # the library's column stride: n rounded up to 64, plus 64 at a power of
+    # two (vectors starting on the same HBM channel slow multi-vector streams)
+    ld = (n + 63) // 64 * 64
+    if ld & (ld - 1) == 0 or ld % 4096 == 0:
+        ld += 64
     src = torch.ones(8 * ld, dtype=torch.float64, device="cuda:0")
     dst = torch.empty(2 * ld, dtype=torch.float64, device="cuda:0")
     sink = torch.empty(4096, dtype=torch.float64, device="cuda:0")
