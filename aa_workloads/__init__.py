@@ -116,6 +116,7 @@ SEED_POISSON1D_B = 1
 SEED_POISSON3D_F = 2
 SEED_QR_Q = 3
 SEED_QR_V = 4
+SEED_EM = 5
 SEED_TRAIN_BASE = 1_000_000
 
 
@@ -160,3 +161,50 @@ def batch_problem(inst: BatchInstance) -> StencilProblem:
 
 def batch_table(count: int = 4096, first_seed: int = 0, **kw) -> list[BatchInstance]:
     return [batch_instance(first_seed + j, **kw) for j in range(count)]
+
+
+# --------------------------------------------------------------------------
+# Expectation-maximization of the means of a univariate normal mixture
+# (the paper's Sec. 5.3): three components with known proportions alpha and
+# standard deviations sigma, unknown means, unlabeled samples.  The AA vector
+# holds R replicas of the three means; the map updates the means of the
+# first replica and writes the result to every replica (Sec. 5.3 estimates one
+# set of means redundantly in every entry).  This module only draws the
+# samples and the starting point; the map itself lives in the oracle and in
+# the library.
+# --------------------------------------------------------------------------
+
+@dataclass
+class EMProblem:
+    samples: np.ndarray          # N draws from the mixture
+    alpha: tuple = (0.3, 0.3, 0.4)
+    sigma: tuple = (1.0, 1.0, 1.0)
+    mu_true: tuple = (0.0, 0.5, 1.0)
+    replicas: int = 1
+
+    @property
+    def n(self) -> int:
+        return 3 * self.replicas
+
+    def u0(self) -> np.ndarray:
+        """Starting means: the samples' 1/6, 1/2 and 5/6 quantiles (distinct,
+        ordered, no constant chosen by hand), replicated."""
+        q = np.quantile(self.samples, [1.0 / 6.0, 0.5, 5.0 / 6.0])
+        return np.tile(q, self.replicas)
+
+
+def em_problem(nsamples: int = 100_000, replicas: int = 500_000, seed: int = SEED_EM,
+               alpha=(0.3, 0.3, 0.4), sigma=(1.0, 1.0, 1.0), mu=(0.0, 0.5, 1.0)) -> EMProblem:
+    """Samples of the mixture sum_i alpha_i N(mu_i, sigma_i^2): component
+    i of sample k from uniform k of stream 0 (the first i with u < alpha_0 +
+    .. + alpha_i), the value mu_i + sigma_i z_k with z_k normal k of stream 1.
+    Defaults: the paper's poorly separated mixture, 100,000 samples, 500,000
+    replicas (1.5 million entries, the paper's vector per GPU)."""
+    u = uniform(seed, 0, nsamples)
+    cum = np.cumsum(alpha)
+    comp = np.searchsorted(cum, u, side="right")
+    comp = np.minimum(comp, len(alpha) - 1)
+    z = normal(seed, 1, nsamples)
+    x = np.asarray(mu)[comp] + np.asarray(sigma)[comp] * z
+    return EMProblem(samples=x, alpha=tuple(alpha), sigma=tuple(sigma), mu_true=tuple(mu),
+                     replicas=replicas)

@@ -89,6 +89,8 @@ def lib():
         L.or_G_stencil.argtypes = [C.c_int, C.c_int64, C.c_double, C.c_double,
                                    C.c_double, P, P, P]
         L.or_G_stencil.restype = None
+        L.or_G_em.argtypes = [C.c_int64, P, P, C.c_int64, P, P, P]
+        L.or_G_em.restype = None
         L.or_laplacian.argtypes = [C.c_int, C.c_int64, C.c_double, P, P]
         L.or_laplacian.restype = None
         L.or_gmres.argtypes = [C.c_int64, P, C.c_int, C.c_int64, C.c_double,
@@ -272,6 +274,18 @@ def G_stencil(prob, u) -> np.ndarray:
     out = np.empty_like(u)
     lib().or_G_stencil(prob.d, prob.s, prob.h, prob.omega, prob.c, _ptr(f),
                        _ptr(u), _ptr(out))
+    return out
+
+
+def G_em(prob, u) -> np.ndarray:
+    """The EM map of Sec. 5.3 for an ``aa_workloads.EMProblem``: the means in
+    u[0:3] updated from the samples, written to every replica."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    x = np.ascontiguousarray(prob.samples, dtype=np.float64)
+    a = np.ascontiguousarray(prob.alpha, dtype=np.float64)
+    sg = np.ascontiguousarray(prob.sigma, dtype=np.float64)
+    out = np.empty_like(u)
+    lib().or_G_em(u.shape[0], _ptr(u), _ptr(x), x.shape[0], _ptr(a), _ptr(sg), _ptr(out))
     return out
 
 

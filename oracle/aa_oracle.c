@@ -671,6 +671,42 @@ void or_laplacian(int d, int64_t s, double h, const double *u, double *y) {
 }
 
 /* ------------------------------------------------------------------ */
+/* expectation-maximization of a normal mixture's means (Sec. 5.3)     */
+/* ------------------------------------------------------------------ */
+
+/* The EM update of the three means of a univariate mixture with known
+ * proportions alpha and standard deviations sigma, from N samples x (Sec.
+ * 5.3): with the current means mu (the first three entries of u),
+ *   p_i(x_k) = alpha_i / (sqrt(2 pi) sigma_i) exp(-(x_k - mu_i)^2 / (2 sigma_i^2)),
+ *   w_ik = p_i(x_k) / sum_j p_j(x_k),
+ *   G(mu)_i = sum_k x_k w_ik / sum_k w_ik,
+ * each sum over k compensated.  The result is written to every replica:
+ * out[3 r + i] = G(mu)_i, r < n / 3. */
+void or_G_em(int64_t n, const double *u, const double *x, int64_t N, const double *alpha,
+             const double *sigma, double *out) {
+  double num[3] = {0, 0, 0}, numc[3] = {0, 0, 0}, den[3] = {0, 0, 0}, denc[3] = {0, 0, 0};
+  const double inv_sqrt_2pi = 0.39894228040143267793994605993438;
+  for (int64_t k = 0; k < N; ++k) {
+    double p[3], tot = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      double d = x[k] - u[i];
+      p[i] = alpha[i] * inv_sqrt_2pi / sigma[i] * exp(-(d * d) / (2.0 * sigma[i] * sigma[i]));
+      tot += p[i];
+    }
+    for (int i = 0; i < 3; ++i) {
+      double w = p[i] / tot;
+      neumaier_add(&num[i], &numc[i], x[k] * w);
+      neumaier_add(&den[i], &denc[i], w);
+    }
+  }
+  double g[3];
+  for (int i = 0; i < 3; ++i) g[i] = (num[i] + numc[i]) / (den[i] + denc[i]);
+  OR_PARALLEL_FOR
+  for (int64_t r = 0; r < n / 3; ++r)
+    for (int i = 0; i < 3; ++i) out[3 * r + i] = g[i];
+}
+
+/* ------------------------------------------------------------------ */
 /* GMRES (Saad and Schultz), used to pin AA through its equivalence    */
 /* with GMRES for linear maps (Sec. 1).  Textbook form: Arnoldi with   */
 /* modified Gram-Schmidt, Givens rotations on the Hessenberg matrix.   */
