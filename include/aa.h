@@ -434,6 +434,28 @@ aa_status aa_fill_uniform(double *d_out, int64_t n, uint64_t seed,
 aa_status aa_fill_normal(double *d_out, int64_t n, uint64_t seed,
                          uint64_t stream_id, uint64_t offset, void *stream);
 
+/* The EM map of Sec. 5.3 (the paper's third test problem): the means of a
+ * three-component univariate normal mixture with known proportions alpha and
+ * standard deviations sigma, estimated from unlabeled samples.  With the
+ * current means mu = d_u[0..2],
+ *   w_ik = alpha_i N(x_k; mu_i, sigma_i^2) / sum_j alpha_j N(x_k; mu_j, sigma_j^2),
+ *   G(mu)_i = sum_k x_k w_ik / sum_k w_ik,
+ * written to every replica: d_out[3 r + i] = G(mu)_i for r < n / 3 (the
+ * paper estimates one set of means redundantly in every entry of the AA
+ * vector, so the map costs O(nsamples + n)).  d_x: nsamples doubles
+ * (device); d_u, d_out: n doubles, n a positive multiple of 3 (d_out may
+ * alias d_u); d_work: at least AA_EM_WORK_DOUBLES doubles of device scratch
+ * owned by the caller.  alpha_i > 0, sigma_i > 0.  Sums in a fixed order
+ * (deterministic).  Asynchronous on `stream`. */
+#define AA_EM_WORK_DOUBLES 6144
+typedef struct {
+  double alpha[3];
+  double sigma[3];
+} aa_em_mixture;
+aa_status aa_em_apply(const aa_em_mixture *h_mix, const double *d_x, int64_t nsamples,
+                      const double *d_u, double *d_out, int64_t n, double *d_work,
+                      void *stream);
+
 /* Measurement: the sustained HBM bandwidth of an access pattern, with the
  * streaming passes' tiles, loads, stores and launch shape (at most 1024
  * workgroups, one resident round).  Reads `reads` vectors of length n from

@@ -37,8 +37,9 @@ SYMBOLS = [
     "aa_mlp_workspace_size", "aa_mlp_init", "aa_mlp_reseed", "aa_mlp_set_params",
     "aa_mlp_get_params", "aa_mlp_get_grads", "aa_mlp_forward", "aa_mlp_backward",
     "aa_mlp_adam", "aa_mlp_destroy", "aa_batch_run_learned", "aa_batch_train",
-    "aa_batch_read_learning", "aa_qr_solve_noalloc", "aa_bandwidth_probe",
+    "aa_batch_read_learning", "aa_qr_solve_noalloc", "aa_bandwidth_probe", "aa_em_apply",
 ]
+EM_WORK_DOUBLES = 6144
 
 BATCH_LEARNED = 1 << 9
 
@@ -62,6 +63,10 @@ class BatchInstance(C.Structure):
     _fields_ = [("n", C.c_int64), ("m", C.c_int), ("dim", C.c_int), ("s", C.c_int64),
                 ("h", C.c_double), ("omega", C.c_double), ("c", C.c_double),
                 ("d_f", C.c_void_p), ("d_x", C.c_void_p)]
+
+
+class EmMixture(C.Structure):
+    _fields_ = [("alpha", C.c_double * 3), ("sigma", C.c_double * 3)]
 
 
 class BatchSchedule(C.Structure):
@@ -101,6 +106,7 @@ def lib():
         "aa_qr_solve": [P, P, P],
         "aa_qr_solve_noalloc": [P, I64, I64, I, P, I, P, P, P],
         "aa_bandwidth_probe": [I, I, P, I64, P, I64, P, P],
+        "aa_em_apply": [C.POINTER(EmMixture), P, I64, P, P, I64, P, P],
         "aa_get_qr": [P, P, P, C.POINTER(C.c_int)],
         "aa_qr_basis": [P, C.POINTER(P), C.POINTER(I64)],
         "aa_qr_load": [P, I, P, I64, P, P],
@@ -206,6 +212,12 @@ def aa_qr_solve(ctx, f, gamma):
 def aa_bandwidth_probe(reads, writes, src, ld, dst, n, sink, stream=None):
     _check(lib().aa_bandwidth_probe(reads, writes, _ptr(src), ld, _ptr(dst), n, _ptr(sink),
                                     _stream(stream)), "aa_bandwidth_probe")
+
+
+def aa_em_apply(alpha, sigma, x, u, out, work, stream=None):
+    mix = EmMixture((C.c_double * 3)(*alpha), (C.c_double * 3)(*sigma))
+    _check(lib().aa_em_apply(C.byref(mix), _ptr(x), x.numel(), _ptr(u), _ptr(out), u.numel(),
+                             _ptr(work), _stream(stream)), "aa_em_apply")
 
 
 def aa_qr_solve_noalloc(Q, ldq, n, k, R, ldr, f, gamma, stream=None):

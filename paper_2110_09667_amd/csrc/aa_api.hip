@@ -967,6 +967,16 @@ aa_status aa_fill_normal(double* out, int64_t n, uint64_t seed, uint64_t stream_
   return hip_ok(launch_fill_normal(out, n, seed, stream_id, offset, (hipStream_t)stream));
 }
 
+aa_status aa_em_apply(const aa_em_mixture* mix, const double* x, int64_t nsamples,
+                      const double* u, double* out, int64_t n, double* work, void* stream) {
+  if (!mix || !x || !u || !out || !work || nsamples < 1 || n < 3 || n % 3 != 0)
+    return AA_EINVAL;
+  for (int i = 0; i < 3; ++i)
+    if (!(mix->alpha[i] > 0.0) || !(mix->sigma[i] > 0.0)) return AA_EINVAL;
+  return hip_ok(launch_em(mix->alpha, mix->sigma, x, nsamples, u, out, n, work,
+                          (hipStream_t)stream));
+}
+
 aa_status aa_bandwidth_probe(int reads, int writes, const double* src, int64_t ld, double* dst,
                              int64_t n, double* sink, void* stream) {
   if (n < 1 || ld < n || !src || (writes > 0 && !dst) || (writes == 0 && !sink)) return AA_EINVAL;

@@ -248,6 +248,9 @@ hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t);
 // problems and generators (aa_problems.hip)
 hipError_t launch_stencil(int dim, int64_t s, double h, double omega, double c,
                           const double* f, const double* u, double* out, hipStream_t);
+// the EM map of Sec. 5.3; work: 6 x min(ceil(N / 256), 1024) doubles
+hipError_t launch_em(const double alpha[3], const double sigma[3], const double* x, int64_t N,
+                     const double* u, double* out, int64_t n, double* work, hipStream_t);
 hipError_t launch_fill_uniform(double* out, int64_t n, uint64_t seed, uint64_t stream_id,
                                uint64_t offset, double lo, double hi, hipStream_t);
 hipError_t launch_fill_normal(double* out, int64_t n, uint64_t seed, uint64_t stream_id,

@@ -104,6 +104,106 @@ __global__ void k_fill_normal(double* out, int64_t n, uint64_t base, uint64_t of
     out[i] = normal_at(base, offset + (uint64_t)i);
 }
 
+// ---------------------------------------------------------------------------
+// EM update of a three-component normal mixture's means (Sec. 5.3)
+// ---------------------------------------------------------------------------
+
+struct EmArgs {
+  const double* x; int64_t N;      // samples
+  const double* u;                 // current vector: the means are u[0..2]
+  double coef[3];                  // alpha_i / (sqrt(2 pi) sigma_i)
+  double inv2s2[3];                // 1 / (2 sigma_i^2)
+  double* partials;                // [6][grid]: sum x w_i, then sum w_i
+};
+
+constexpr int kEmWG = 256;
+constexpr int kEmMaxGrid = 1024;
+
+// Per sample k: p_i = alpha_i / (sqrt(2 pi) sigma_i) exp(-(x_k - mu_i)^2 /
+// (2 sigma_i^2)), w_i = p_i / sum_j p_j; each lane accumulates x_k w_i and
+// w_i over its samples (grid stride), then one fixed-order reduction per
+// workgroup writes the workgroup's six partial sums.
+__global__ __launch_bounds__(kEmWG) void k_em_partials(EmArgs a) {
+  const double m0 = a.u[0], m1 = a.u[1], m2 = a.u[2];
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t k = (int64_t)blockIdx.x * kEmWG + threadIdx.x; k < a.N;
+       k += (int64_t)gridDim.x * kEmWG) {
+    const double x = a.x[k];
+    const double d0 = x - m0, d1 = x - m1, d2 = x - m2;
+    const double p0 = a.coef[0] * exp(-(d0 * d0) * a.inv2s2[0]);
+    const double p1 = a.coef[1] * exp(-(d1 * d1) * a.inv2s2[1]);
+    const double p2 = a.coef[2] * exp(-(d2 * d2) * a.inv2s2[2]);
+    const double tot = p0 + p1 + p2;
+    const double w0 = p0 / tot, w1 = p1 / tot, w2 = p2 / tot;
+    acc[0] += x * w0;
+    acc[1] += x * w1;
+    acc[2] += x * w2;
+    acc[3] += w0;
+    acc[4] += w1;
+    acc[5] += w2;
+  }
+  const double r = multi_reduce<8>(acc);  // lane l < 8: value l over the wave
+  __shared__ double s_w[kEmWG / 64][8];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane < 8) s_w[w][lane] = r;
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double t = 0.0;
+    for (int q = 0; q < kEmWG / 64; ++q) t += s_w[q][threadIdx.x];
+    a.partials[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// Every workgroup sums the G partials of the six values in the same fixed
+// order (so all agree bit for bit), forms G(mu)_i = sum x w_i / sum w_i and
+// writes its share of the replicas: out[3 r + i] = G(mu)_i.
+__global__ __launch_bounds__(kEmWG) void k_em_broadcast(const double* __restrict__ partials,
+                                                        int G, double* __restrict__ out,
+                                                        int64_t nrep) {
+  __shared__ double s_g[3];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (w == 0) {
+    double t[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      double v = 0.0;
+      for (int g = lane; g < G; g += 64) v += partials[(size_t)c * G + g];
+      t[c] = wave_sum(v);
+    }
+    if (lane < 3) s_g[lane] = t[lane] / t[lane + 3];
+  }
+  __syncthreads();
+  const double g0 = s_g[0], g1 = s_g[1], g2 = s_g[2];
+  for (int64_t r = (int64_t)blockIdx.x * kEmWG + threadIdx.x; r < nrep;
+       r += (int64_t)gridDim.x * kEmWG) {
+    out[3 * r] = g0;
+    out[3 * r + 1] = g1;
+    out[3 * r + 2] = g2;
+  }
+}
+
+hipError_t launch_em(const double alpha[3], const double sigma[3], const double* x, int64_t N,
+                     const double* u, double* out, int64_t n, double* work, hipStream_t st) {
+  (void)hipGetLastError();  // drop a stale error left by an earlier call
+  EmArgs a{};
+  a.x = x;
+  a.N = N;
+  a.u = u;
+  for (int i = 0; i < 3; ++i) {
+    a.coef[i] = alpha[i] * 0.39894228040143267793994605993438 / sigma[i];
+    a.inv2s2[i] = 1.0 / (2.0 * sigma[i] * sigma[i]);
+  }
+  a.partials = work;
+  int64_t g = (N + kEmWG - 1) / kEmWG;
+  const int G = (int)(g > kEmMaxGrid ? kEmMaxGrid : g);
+  hipLaunchKernelGGL(k_em_partials, dim3(G), dim3(kEmWG), 0, st, a);
+  const int64_t nrep = n / 3;
+  int64_t gb = (nrep + kEmWG - 1) / kEmWG;
+  const int GB = (int)(gb > 2048 ? 2048 : (gb < 1 ? 1 : gb));
+  hipLaunchKernelGGL(k_em_broadcast, dim3(GB), dim3(kEmWG), 0, st, work, G, out, nrep);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_uniform(double* out, int64_t n, uint64_t seed, uint64_t stream_id,
                                uint64_t offset, double lo, double hi, hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
