@@ -27,8 +27,12 @@
  *   One context must not be used from two host threads at once.
  * - Errors: every entry point returns an aa_status.  Argument and state errors
  *   are detected on the host before anything is enqueued and leave the context
- *   unchanged.  Device-side breakdown (a zero, negative or non-finite R_kk) is
- *   latched in the workspace and reported by the next aa_get_info.  The
+ *   unchanged.  Device-side breakdown (the new column numerically in the span
+ *   of the window: R_kk <= 64 eps ||R_{0:k,k}||, or non-finite) is latched in
+ *   the workspace and reported by the next aa_get_info.  In aa_step a
+ *   breakdown ends the iteration: that step returns x_{i+1} = G(x_i) (no
+ *   extrapolation from the broken factorization) and later steps change
+ *   nothing until aa_reset, which restarts AA from the current iterate.  The
  *   library never aborts and never prints.
  */
 #ifndef AA_H
@@ -66,7 +70,9 @@ typedef enum {
   AA_OK = 0,
   AA_EINVAL = -1,      /* bad argument (size, pointer, alignment, enum)     */
   AA_EHIP = -2,        /* a HIP runtime call failed                          */
-  AA_EBREAKDOWN = -3,  /* R_kk <= 0 or non-finite: F_i lost full column rank */
+  AA_EBREAKDOWN = -3,  /* F_i lost full column rank: the new column's R_kk
+                          is at most 64 eps times its column norm (or zero,
+                          negative, non-finite)                              */
   AA_ESTATE = -4,      /* QRAdd on a full window, QRDelete on an empty one   */
   AA_ENOSPACE = -5     /* workspace smaller than aa_workspace_size           */
 } aa_status;
@@ -118,6 +124,21 @@ enum {
  * more column in the QRAdd microbenchmark. */
 #define AA_MAX_COLS 65
 
+/* Why an iteration has ended (aa_info.stopped). */
+enum {
+  AA_RUNNING = 0,
+  AA_STOPPED_TEST = 1,      /* the stopping test of aa_set_stop held        */
+  AA_STOPPED_BREAKDOWN = 2, /* a breakdown (status AA_EBREAKDOWN)           */
+  AA_STOPPED_CAP = 3        /* the iteration cap of aa_set_stop was reached */
+};
+
+/* Stopping tests of aa_set_stop (Alg. 1 stops on the step length; the
+ * workloads stop on the relative residual, reading A2). */
+enum {
+  AA_STOP_RESIDUAL = 0,     /* ||f_i||_2 <= tol ||f_0||_2 at the start of i  */
+  AA_STOP_STEP = 1          /* ||x_i - x_{i-1}||_2 < tol at the start of i   */
+};
+
 typedef struct {
   int64_t iter;      /* index i of the next aa_step call                    */
   int m_i;           /* columns used by the last step (min(m, i))           */
@@ -126,6 +147,10 @@ typedef struct {
   double res0_norm;  /* ||f_0||_2                                           */
   double step_norm;  /* ||x_{i+1} - x_i||_2 of the last step                */
   int status;        /* AA_OK or a latched device-side error                */
+  int stopped;       /* AA_RUNNING or why the iteration ended               */
+  int64_t stop_iter; /* the iteration i at which it ended (x_i is the
+                        answer of a stopping test or cap; G(x_i) was
+                        returned by the step that broke down)               */
 } aa_info;
 
 /* Bytes of device workspace for a window of m columns over vectors of
@@ -165,6 +190,18 @@ aa_status aa_set_graph(aa_ctx *ctx, int enable);
 
 /* Waits for the context's stream and reports the state of the last step. */
 aa_status aa_get_info(aa_ctx *ctx, aa_info *h_info);
+
+/* Stopping rule of aa_step (Alg. 1's tol and maxIters), evaluated on the
+ * device so that a driver loop needs no per-step synchronization: with mode
+ * AA_STOP_RESIDUAL the iteration ends at the start of iteration i >= 1 when
+ * ||f_i||_2 <= tol ||f_0||_2; with AA_STOP_STEP when ||x_i - x_{i-1}||_2 < tol
+ * (the paper's test on the step, in the 2-norm).  tol <= 0 disables the
+ * test.  max_iter >= 1 caps the iterations i (0: no cap).  Once the iteration
+ * has ended (test, cap or breakdown) every further aa_step leaves the state
+ * unchanged and writes x_next = x (the host enqueues the same launches; they
+ * return at once), and aa_get_info reports why and at which i; aa_reset
+ * starts over.  Defaults: no test, no cap. */
+aa_status aa_set_stop(aa_ctx *ctx, double tol, int64_t max_iter, int mode);
 
 /* QRAdd (Alg. 2 with Alg. 3, 4, 5 or 6): append d_v (length n, not modified)
  * as column k; k -> k + 1.  AA_ESTATE if k == m. */

@@ -154,6 +154,11 @@ typedef struct {
 #define RM(s, i, j) ((s)->R[(i) + (int64_t)(j) * (s)->cap])
 #define TM(s, i, j) ((s)->T[(i) + (int64_t)(j) * (s)->cap])
 
+/* Breakdown: the new column's R_kk at most 64 eps times the norm of its
+ * column of R (the column numerically in the span of the window; the paper
+ * does not treat rank deficiency, reading A10). */
+#define OR_BREAKDOWN_REL (64.0 * 2.220446049250313e-16)
+
 /* Final normalization shared by every QRAdd variant (last two lines of
  * Algs. 3-6): R_kk = ||v||_2 (one Sync), q_k = v / R_kk. */
 static int normalize_into(or_qr *s, double *v) {
@@ -161,7 +166,9 @@ static int normalize_into(or_qr *s, double *v) {
   double nv = nrm2(s->n, v);
   s->syncs_add += 1;
   RM(s, k, k) = nv;
-  if (!(nv > 0.0) || !isfinite(nv)) return OR_EBREAKDOWN;
+  double col = nv * nv;
+  for (int j = 0; j < k; ++j) col += RM(s, j, k) * RM(s, j, k);
+  if (!(nv > OR_BREAKDOWN_REL * sqrt(col)) || !isfinite(nv)) return OR_EBREAKDOWN;
   double *q = QCOL(s, k);
   OR_PARALLEL_FOR
   for (int64_t r = 0; r < s->n; ++r) q[r] = v[r] / nv;
@@ -302,7 +309,7 @@ static int qr_add_dcgs2_lag(or_qr *s, double *v) {
   }
   double rho2 = alpha - ss;
   int st = OR_OK;
-  if (!(rho2 > 0.0) || !isfinite(rho2)) {
+  if (!(rho2 > OR_BREAKDOWN_REL * alpha) || !isfinite(rho2)) {
     st = OR_EBREAKDOWN;
   } else {
     double rho = sqrt(rho2);
@@ -321,10 +328,12 @@ static int qr_add_dcgs2_lag(or_qr *s, double *v) {
     RM(s, p, k) = rpk;
     rr += rpk * rpk;
     double w2 = nu - rr;
-    if (!(w2 > 0.0) || !isfinite(w2)) {
+    double rkk = sqrt(w2);
+    /* nu - ||r||^2 carries rounding of order eps nu: below 64 eps nu the
+     * new column's norm is noise (it is numerically in the span) */
+    if (!(w2 > OR_BREAKDOWN_REL * nu) || !isfinite(w2)) {
       st = OR_EBREAKDOWN;
     } else {
-      double rkk = sqrt(w2);
       for (int j = 0; j < p; ++j) axmy(n, zc[j], QCOL(s, j), v);
       axmy(n, rpk, qp, v);
       RM(s, k, k) = rkk;
@@ -357,7 +366,7 @@ int or_qr_flush(or_qr *s, int variant) {
   for (int j = 0; j < p; ++j) ss += sc[j] * sc[j];
   double rho2 = alpha - ss;
   int st = OR_OK;
-  if (!(rho2 > 0.0) || !isfinite(rho2)) {
+  if (!(rho2 > OR_BREAKDOWN_REL * alpha) || !isfinite(rho2)) {
     st = OR_EBREAKDOWN;
   } else {
     double rho = sqrt(rho2);

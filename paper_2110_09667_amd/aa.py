@@ -38,6 +38,7 @@ SYMBOLS = [
     "aa_mlp_get_params", "aa_mlp_get_grads", "aa_mlp_forward", "aa_mlp_backward",
     "aa_mlp_adam", "aa_mlp_destroy", "aa_batch_run_learned", "aa_batch_train",
     "aa_batch_read_learning", "aa_qr_solve_noalloc", "aa_bandwidth_probe", "aa_em_apply",
+    "aa_set_stop",
 ]
 EM_WORK_DOUBLES = 6144
 
@@ -56,7 +57,12 @@ class AAError(RuntimeError):
 class Info(C.Structure):
     _fields_ = [("iter", C.c_int64), ("m_i", C.c_int), ("k", C.c_int),
                 ("res_norm", C.c_double), ("res0_norm", C.c_double),
-                ("step_norm", C.c_double), ("status", C.c_int)]
+                ("step_norm", C.c_double), ("status", C.c_int), ("stopped", C.c_int),
+                ("stop_iter", C.c_int64)]
+
+
+RUNNING, STOPPED_TEST, STOPPED_BREAKDOWN, STOPPED_CAP = 0, 1, 2, 3
+STOP_RESIDUAL, STOP_STEP = 0, 1
 
 
 class BatchInstance(C.Structure):
@@ -101,6 +107,7 @@ def lib():
         "aa_set_stream": [P, P],
         "aa_step": [P, P, P, P],
         "aa_get_info": [P, C.POINTER(Info)],
+        "aa_set_stop": [P, D, I64, I],
         "aa_qr_add": [P, P],
         "aa_qr_delete": [P],
         "aa_qr_solve": [P, P, P],
@@ -402,6 +409,10 @@ class AAContext:
     def set_graph(self, enable: bool = True):
         """Replay steady-state iterations from HIP graphs (see aa_set_graph)."""
         _check(lib().aa_set_graph(self.ctx, 1 if enable else 0), "aa_set_graph")
+
+    def set_stop(self, tol: float, max_iter: int = 0, mode: int = 0):
+        """Stopping rule evaluated on the device (see aa_set_stop)."""
+        _check(lib().aa_set_stop(self.ctx, tol, max_iter, mode), "aa_set_stop")
 
     def set_fused_threshold(self, n_max: int):
         aa_set_fused_threshold(self.ctx, n_max)

@@ -31,6 +31,11 @@ struct aa_ctx {
   int64_t iter = 0;
   int k = 0, m_i = 0;
   int64_t syncs_add = 0, syncs_del = 0, syncs_rhs = 0;
+  // stopping rule (aa_set_stop) and its device state
+  StopState* stop_dev = nullptr;
+  int stop_mode = kStopNone;
+  double stop_tol = 0.0;
+  int64_t max_iter = 0;  // 0: no cap
   // fused single-workgroup step for small n (aa_batch.hip)
   BInst* d_binst = nullptr;
   BState* d_bstate = nullptr;
@@ -79,7 +84,7 @@ int64_t leading_dim(int64_t n) {
 struct Layout {
   int64_t ldq;
   size_t off_Q, off_ring, off_W, off_fp, off_gp, off_R, off_T, off_c0, off_c1, off_gam,
-      off_giv, off_scal, off_status, off_part, off_binst, off_bstate, total;
+      off_giv, off_scal, off_status, off_stop, off_part, off_binst, off_bstate, total;
 };
 
 Layout make_layout(int64_t n, int m, unsigned flags) {
@@ -103,6 +108,7 @@ Layout make_layout(int64_t n, int m, unsigned flags) {
   L.off_giv = o; o = align_up(o + sizeof(double) * 2 * cap);
   L.off_scal = o; o = align_up(o + sizeof(double) * S_COUNT);
   L.off_status = o; o = align_up(o + sizeof(int));
+  L.off_stop = o; o = align_up(o + sizeof(StopState));
   const size_t part = kPartials;
   L.off_part = o; o = align_up(o + sizeof(double) * part);
   L.off_binst = o; o = align_up(o + sizeof(BInst));
@@ -359,7 +365,7 @@ aa_status qr_add_impl(aa_ctx* c, const double* v, const double* f = nullptr,
         return AA_EINVAL;
     }
   }
-  ScaleArgs sa{k == 0 ? v : slotk, slotk, c->n, c->sm.R, k, c->sm.cap};
+  ScaleArgs sa{k == 0 ? v : slotk, slotk, c->n, c->sm.R, k, c->sm.cap, c->sm.stop, c->sm.status};
   chk(timed(c, AA_K_SCALE, 2, [&] { return launch_scale(sa, c->sm, st); }));
   if (e != hipSuccess) return AA_EHIP;
   c->k = k + 1;
@@ -509,6 +515,8 @@ aa_status fused_step(aa_ctx* c, const double* x, const double* g, double* x_next
   a.ox = x; a.og = g; a.oxn = x_next;
   a.ov_iter = c->iter;
   a.ov_k = c->k;
+  a.stop_mode = c->stop_mode;
+  a.stop_tol = c->stop_tol;
   const int kb = c->m <= 8 ? 8 : c->m <= 16 ? 16 : c->m <= 32 ? 32 : 64;
   const bool gram = batch_needs_gram(c->variant, c->flags);
   // model bytes and reduction counts of this iteration
@@ -620,7 +628,11 @@ aa_status aa_init(aa_ctx** ctx, int64_t n, int m, int variant, unsigned flags,
   c->sm.status = (int*)(base + L.off_status);
   c->sm.partials = (double*)(base + L.off_part);
   c->sm.cap = m;
-  if (launch_init_small(c->sm, c->stream) != hipSuccess) {
+  c->sm.stop = nullptr;  // set only while an AA step is enqueued
+  c->stop_dev = (StopState*)(base + L.off_stop);
+  Small s0 = c->sm;
+  s0.stop = c->stop_dev;
+  if (launch_init_small(s0, c->stream) != hipSuccess) {
     delete c;
     return AA_EHIP;
   }
@@ -630,6 +642,7 @@ aa_status aa_init(aa_ctx** ctx, int64_t n, int m, int variant, unsigned flags,
     I.n = n; I.ld = c->ldq; I.m = m; I.dim = 0;
     I.f_prev = c->f_prev; I.g_prev = c->g_prev; I.W = c->W; I.Q = c->Q; I.ring = c->ring;
     I.sm = c->sm;
+    I.sm.stop = c->stop_dev;  // the one-workgroup step is an AA step
     BState st{};
     st.conv_iter = -1;
     st.active = 1;
@@ -655,10 +668,18 @@ aa_status aa_set_stream(aa_ctx* c, void* stream) {
 }
 
 
+// While an AA step is enqueued its launches carry the device stop state.
+struct StepScope {
+  aa_ctx* c;
+  explicit StepScope(aa_ctx* cc) : c(cc) { c->sm.stop = c->stop_dev; }
+  ~StepScope() { c->sm.stop = nullptr; }
+};
+
 // One iteration of Alg. 1 enqueued kernel by kernel (host sequencing).
 static aa_status step_enqueue(aa_ctx* c, const double* x, const double* g,
                               double* x_next) {
   if (c->d_binst && c->n <= c->fused_max) return fused_step(c, x, g, x_next);
+  StepScope scope(c);
   const hipStream_t st = c->stream;
   const int G = grid_stream(c);
   if (c->iter == 0) {
@@ -677,8 +698,12 @@ static aa_status step_enqueue(aa_ctx* c, const double* x, const double* g,
   const int slot = (int)((i - 1) % m);
   HistArgs h{x, g, c->W, c->f_prev, c->g_prev, c->ring + (int64_t)slot * c->ldq, nullptr,
              c->n, 0};
+  Tail tr = tail(TAIL_RES, c->k);  // the stopping test at the start of iteration i
+  tr.stop_mode = c->stop_mode;
+  tr.stop_tol = c->stop_tol;
+  tr.m_i = c->m_i;
   if (timed(c, AA_K_HISTORY, 8,
-            [&] { return launch_history(h, c->sm, tail(TAIL_RES, 0), G, st); }) != hipSuccess)
+            [&] { return launch_history(h, c->sm, tr, G, st); }) != hipSuccess)
     return AA_EHIP;
   aa_status s = AA_OK;
   bool rhs_done = false;
@@ -695,8 +720,10 @@ static aa_status step_enqueue(aa_ctx* c, const double* x, const double* g,
   if (s == AA_OK && !rhs_done) s = rhs_impl(c, c->f_prev);  // R gamma = Q^T f_i
   if (s != AA_OK) return s;
   XupdArgs xa{c->ring, c->ldq, m, (int)((i - m_i) % m), m_i, g, x, x_next, c->n, c->sm.gamma};
+  Tail tx = tail(TAIL_STEP, c->k);
+  tx.m_i = m_i;
   if (timed(c, AA_K_XUPDATE, m_i + 3,
-            [&] { return launch_xupdate(xa, c->sm, tail(TAIL_STEP, 0), G, st); }) != hipSuccess)
+            [&] { return launch_xupdate(xa, c->sm, tx, G, st); }) != hipSuccess)
     return AA_EHIP;
   c->m_i = m_i;
   c->iter = i + 1;
@@ -755,10 +782,22 @@ static aa_status step_graph(aa_ctx* c, const double* x, const double* g, double*
 aa_status aa_step(aa_ctx* c, const double* x, const double* g, double* x_next) {
   if (!c || !x || !g || !x_next || (c->flags & AA_QR_ONLY)) return AA_EINVAL;
   if (x_next == g) return AA_EINVAL;
+  if (c->max_iter > 0 && c->iter > c->max_iter)  // the cap: iteration i = max_iter + 1 ends it
+    return hip_ok(launch_stop_cap(c->stop_dev, c->k, c->m_i, x, x_next, c->n, c->stream));
   const bool one_wg = c->d_binst && c->n <= c->fused_max;
   if (c->graph_on && c->stream && !c->prof_on && !one_wg && c->iter > c->m && c->k == c->m)
     return step_graph(c, x, g, x_next);
   return step_enqueue(c, x, g, x_next);
+}
+
+aa_status aa_set_stop(aa_ctx* c, double tol, int64_t max_iter, int mode) {
+  if (!c || !(tol == tol) || max_iter < 0 || (mode != AA_STOP_RESIDUAL && mode != AA_STOP_STEP))
+    return AA_EINVAL;
+  drop_graphs(c);  // captured iterations carry the test in their launch arguments
+  c->stop_tol = tol > 0.0 ? tol : 0.0;
+  c->stop_mode = tol > 0.0 ? (mode == AA_STOP_STEP ? kStopStep : kStopResidual) : kStopNone;
+  c->max_iter = max_iter;
+  return AA_OK;
 }
 
 aa_status aa_set_graph(aa_ctx* c, int enable) {
@@ -773,12 +812,26 @@ aa_status aa_get_info(aa_ctx* c, aa_info* info) {
   if (!c || !info) return AA_EINVAL;
   double sc[S_COUNT];
   int status = 0;
+  StopState stop{};
   if (hipMemcpyAsync(sc, c->sm.scal, sizeof(sc), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
     return AA_EHIP;
   if (hipMemcpyAsync(&status, c->sm.status, sizeof(int), hipMemcpyDeviceToHost, c->stream) !=
       hipSuccess)
     return AA_EHIP;
+  if (hipMemcpyAsync(&stop, c->stop_dev, sizeof(stop), hipMemcpyDeviceToHost, c->stream) !=
+      hipSuccess)
+    return AA_EHIP;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return AA_EHIP;
+  if (stop.done != 0) {
+    // steps enqueued after the end changed nothing on the device: report (and
+    // resume counting from) the state in which the iteration ended
+    drop_graphs(c);
+    c->iter = stop.iter;
+    c->k = stop.k;
+    c->m_i = stop.m_i;
+  }
+  info->stopped = stop.done;
+  info->stop_iter = stop.done ? stop.iter : -1;
   info->iter = c->iter;
   info->m_i = c->m_i;
   info->k = c->k;
@@ -874,7 +927,9 @@ aa_status aa_reset(aa_ctx* c) {
   c->iter = 0;
   c->k = 0;
   c->m_i = 0;
-  return hip_ok(launch_init_small(c->sm, c->stream));
+  Small s0 = c->sm;
+  s0.stop = c->stop_dev;
+  return hip_ok(launch_init_small(s0, c->stream));
 }
 
 aa_status aa_destroy(aa_ctx* c) {

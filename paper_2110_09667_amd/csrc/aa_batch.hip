@@ -381,6 +381,13 @@ __device__ void wg_delete_first_pass(const BInst& I, int variant, unsigned flags
   }
 }
 
+// dst = src over n values by the whole workgroup (nothing when they alias).
+__device__ void wg_copy(const double* src, double* dst, int64_t n) {
+  if (src != dst)
+    for (int64_t r = threadIdx.x; r < n; r += kWG) dst[r] = src[r];
+  __syncthreads();
+}
+
 // Front of one iteration of Alg. 1 for one instance (every thread of the
 // workgroup): G, history formation, the stopping test, QRDelete, QRAdd and
 // R gamma = Q^T f_i.  Returns false when the iteration ends here (the first
@@ -411,7 +418,18 @@ __device__ bool wg_front(const BatchArgs& b, const BInst& I, BState& st, L& lds,
   const int m_i = (int)(it < m ? it : m);
   const int slot = (int)((it - 1) % m);
   HistArgs h{x, g, I.W, I.f_prev, I.g_prev, I.ring + (int64_t)slot * I.ld, nullptr, I.n, 0};
-  wg_pass(sm, mk_tail(TAIL_RES, 0), 1, lds, [&](double* acc) { history_body(h, 0, 1, acc); });
+  Tail tr = mk_tail(TAIL_RES, st.k);
+  if (b.ov_iter >= 0) {  // fused single-instance step: the context's stopping test
+    tr.stop_mode = b.stop_mode;
+    tr.stop_tol = b.stop_tol;
+    tr.m_i = st.m_i;
+  }
+  wg_pass(sm, tr, 1, lds, [&](double* acc) { history_body(h, 0, 1, acc); });
+  if (b.ov_iter >= 0 && sm.stop && sm.stop->done != 0) {
+    // the test held at the start of this iteration: x_next = x_i
+    wg_copy(x, xn, I.n);
+    return false;
+  }
   const double res = sqrt(sm.scal[S_RES]);
   st.res_norm = res;
   st.status = *sm.status;
@@ -666,7 +684,18 @@ __device__ BState wg_instance(const BatchArgs& b, const BInst& I, BState st, L& 
     }
     default: {
       if (wg_front<KB, GRAM>(b, I, st, lds, x, xn, g)) {
-        wg_plain_update(I, st, lds, x, xn, g);
+        if (b.ov_iter >= 0 && I.sm.stop && *I.sm.status != AA_OK) {
+          // breakdown in this iteration: x_{i+1} = G(x_i), and it ends here
+          wg_copy(g, xn, I.n);
+          if (threadIdx.x == 0) {
+            I.sm.stop->iter = I.sm.stop->cur - 1;
+            I.sm.stop->k = st.k;
+            I.sm.stop->m_i = st.m_i;
+            I.sm.stop->done = AA_STOPPED_BREAKDOWN;
+          }
+        } else {
+          wg_plain_update(I, st, lds, x, xn, g);
+        }
         st.iter += 1;
       }
       return st;
@@ -684,6 +713,10 @@ __global__ __launch_bounds__(kWG, 2) void k_batch(BatchArgs b) {
   __shared__ L lds;
   __shared__ int s_idx;
   if (b.ov_iter >= 0) {  // fused single-instance step: host-held counters
+    if (aa_stopped(b.inst[0].sm)) {  // the iteration has ended: x_next = x
+      wg_copy(b.ox, b.oxn, b.inst[0].n);
+      return;
+    }
     BState st = b.state[0];
     st.iter = b.ov_iter;
     st.k = b.ov_k;

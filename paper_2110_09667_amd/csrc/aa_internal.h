@@ -48,6 +48,19 @@ enum TailOp : int {
                   // column, project the new one (R, coef0, coef1, S_RHO, S_RKK)
 };
 
+// Stop state of an AA iteration on the device (single-instance contexts).
+// done: 0 running; AA_STOPPED_TEST (the stopping test held at the start of
+// iteration `iter`, with k columns and window m_i); AA_STOPPED_BREAKDOWN (a
+// breakdown in iteration `iter`); AA_STOPPED_CAP (the iteration cap).
+struct StopState {
+  int done;
+  int k;
+  int m_i;
+  int pad;
+  int64_t iter;
+  int64_t cur;  // index i of the iteration the device is in (graph-safe count)
+};
+
 // Device-resident small dense state (pointers into the workspace).
 struct Small {
   double* R;        // cap x cap, column-major
@@ -60,7 +73,22 @@ struct Small {
   int* status;      // latched aa_status
   double* partials; // reduction partials, [nred][grid]
   int cap;
+  // AA step launches only (null otherwise): once done is set or a breakdown
+  // is latched in status, every kernel of the step returns at once, and the
+  // x update writes x_next = x (or G(x) in the step that broke down)
+  StopState* stop;
 };
+
+enum StopMode : int { kStopNone = 0, kStopResidual = 1, kStopStep = 2 };
+
+// Breakdown: the new column's R_kk at most this multiple of eps times the
+// norm of its R column (the column numerically in the span of the window).
+constexpr double kBreakdownRel = 64.0 * 2.220446049250313e-16;
+
+// Whether the AA iteration this launch belongs to has ended.
+__device__ __forceinline__ bool aa_stopped(const Small& sm) {
+  return sm.stop != nullptr && (sm.stop->done != 0 || *sm.status != AA_OK);
+}
 
 struct Tail {
   int op;
@@ -74,6 +102,11 @@ struct Tail {
   int zoff;     // first QRAdd pass with rhs: index of Q^T f in red[]
   int inner;    // TAIL_GRAM_ADD: the QRAdd first-pass tail to run afterwards
   int gram_t;   // TAIL_GRAM_ADD: also refresh T from the Gram (ICWY)
+  // TAIL_RES in an AA step: the stopping test (Alg. 1, reading A2) at the
+  // start of the iteration, with k columns and window m_i (host values)
+  int stop_mode;     // kStopNone, kStopResidual, kStopStep
+  double stop_tol;
+  int m_i;
 };
 
 // ---- streaming passes -------------------------------------------------------
@@ -139,7 +172,10 @@ __host__ __device__ inline int gram_cols(const RotArgs& a) {
   return a.k - 1 - a.drop_last + a.naug;
 }
 
-struct ScaleArgs { const double* in; double* out; int64_t n; const double* R; int kk; int cap; };
+struct ScaleArgs {
+  const double* in; double* out; int64_t n; const double* R; int kk; int cap;
+  const StopState* stop; const int* status;  // AA step launches: skip once stopped
+};
 
 struct HistArgs {        // i >= 1: history formation; i == 0: first step
   const double* x; const double* g;
@@ -205,6 +241,8 @@ struct BatchArgs {
   const double* ox; const double* og; double* oxn;
   int64_t ov_iter; int ov_k;
   int mode;               // BatchMode
+  int stop_mode;          // fused single-instance step: the stopping test
+  double stop_tol;
   float* feat;            // [count x kFeat] network inputs (phase A)
   const float* out;       // [count x kOuts] network outputs (guard / train)
   float* dout;            // [count x kOuts] loss gradient (train)
@@ -244,6 +282,8 @@ hipError_t launch_init_small(const Small&, hipStream_t);
 hipError_t launch_probe(int reads, int writes, const double* src, int64_t ld, double* dst,
                         int64_t n, double* sink, int grid, hipStream_t);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t);
+hipError_t launch_stop_cap(StopState* stop, int k, int m_i, const double* x, double* xn,
+                           int64_t n, hipStream_t);
 
 // problems and generators (aa_problems.hip)
 hipError_t launch_stencil(int dim, int64_t s, double h, double omega, double c,

@@ -52,6 +52,17 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int
 // value, two values per wave in flight), then the dense tail.
 __global__ __launch_bounds__(kFinWG) void k_finalize(Small sm, Tail t, int nred, int G) {
   __shared__ double red[kMaxRedAll];
+  if (sm.stop) {
+    // the x update's finalize ends an iteration that broke down (its x update
+    // wrote G(x_i)); the iteration counter already names the next one
+    if (t.op == TAIL_STEP && threadIdx.x == 0 && sm.stop->done == 0 && *sm.status != AA_OK) {
+      sm.stop->iter = sm.stop->cur - 1;
+      sm.stop->k = t.k;
+      sm.stop->m_i = t.m_i;
+      sm.stop->done = AA_STOPPED_BREAKDOWN;
+    }
+    if (aa_stopped(sm)) return;
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   constexpr int waves = kFinWG / 64;
   for (int c = w; c < nred; c += 2 * waves) {
@@ -93,6 +104,7 @@ __global__ __launch_bounds__(kFinWG) void k_finalize(Small sm, Tail t, int nred,
 }
 
 __global__ __launch_bounds__(kWG) void k_dots(DotsArgs a, Small sm) {
+  if (aa_stopped(sm)) return;
   __shared__ double s_acc[kWaves * kMaxRed];
   lds_zero(s_acc, kWaves * kMaxRed);
   __syncthreads();
@@ -110,6 +122,7 @@ __global__ __launch_bounds__(kWG) void k_dots(DotsArgs a, Small sm) {
 #endif
 template <int KQ, int NR>
 __global__ __launch_bounds__(kWG) void k_dots_reg(DotsArgs a, Small sm) {
+  if (aa_stopped(sm)) return;
   constexpr int STR = NR * KQ + 2;  // nx + ny + nz + xx + xz <= NR KQ + 2
   __shared__ double s_acc[kWaves * STR];
   lds_zero(s_acc, kWaves * STR);
@@ -119,6 +132,7 @@ __global__ __launch_bounds__(kWG) void k_dots_reg(DotsArgs a, Small sm) {
 }
 
 __global__ __launch_bounds__(kWG) void k_update(UpdArgs a, Small sm) {
+  if (aa_stopped(sm)) return;
   __shared__ double s_c1[kMaxCols], s_c2[kMaxCols], s_s[kMaxCols];
   __shared__ double s_acc[kWaves * 4];
   update_coefs(a, s_c1, s_c2, s_s);
@@ -130,6 +144,7 @@ __global__ __launch_bounds__(kWG) void k_update(UpdArgs a, Small sm) {
 
 template <int KMAX>
 __global__ __launch_bounds__(kWG) void k_cgs2b(Cgs2bArgs a, Small sm) {
+  if (aa_stopped(sm)) return;
   __shared__ double s_s[KMAX];
   __shared__ double s_acc[kWaves * KMAX];
   for (int j = threadIdx.x; j < KMAX; j += kWG) s_s[j] = (j < a.k) ? a.s[j] : 0.0;
@@ -140,6 +155,7 @@ __global__ __launch_bounds__(kWG) void k_cgs2b(Cgs2bArgs a, Small sm) {
 }
 
 __global__ __launch_bounds__(64) void k_givens(Small sm, int k, int transform) {
+  if (aa_stopped(sm)) return;
   __shared__ double H[kMaxCols * kMaxCols];
   givens_body(sm, k, H);
   if (transform) {
@@ -149,6 +165,7 @@ __global__ __launch_bounds__(64) void k_givens(Small sm, int k, int transform) {
 }
 
 __global__ __launch_bounds__(kWG) void k_rotate(RotArgs a, Small sm) {
+  if (aa_stopped(sm)) return;
   __shared__ double s_c[kMaxCols], s_s[kMaxCols];
   givens_coefs(a, sm.cap, s_c, s_s, kMaxCols);
   __syncthreads();
@@ -174,6 +191,7 @@ constexpr int kRotChMid = AA_ROT_CH_MID;
 
 template <int KMAX, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_rotate_gram(RotArgs a, Small sm) {
+  if (aa_stopped(sm)) return;
   // staging rows, then the per-wave pair sums: gram_lds_doubles(gram_cols(a), WAVES)
   extern __shared__ double s_buf[];
   __shared__ double s_c[KMAX], s_s[KMAX];
@@ -217,6 +235,7 @@ __host__ __device__ constexpr int gram_split_lds_doubles(int na) {
 }
 
 __global__ __launch_bounds__(kWG) void k_rotate_gram_split(RotArgs a, Small sm) {
+  if (aa_stopped(sm)) return;
   extern __shared__ double s_buf[];
   __shared__ double s_c[64], s_s[64];
   const int na = gram_cols(a), np = na * (na - 1) / 2;
@@ -236,6 +255,7 @@ constexpr int kGramSmall = 8;
 
 template <int NAMAX>
 __global__ __launch_bounds__(kWG) void k_rotate_gram_small(RotArgs a, Small sm) {
+  if (aa_stopped(sm)) return;
   constexpr int NR = NAMAX == 4 ? 8 : 32;  // NAMAX (NAMAX - 1) / 2 pairs, padded
   __shared__ double s_c[NAMAX], s_s[NAMAX];
   __shared__ double s_acc[kWaves * NR];
@@ -251,10 +271,12 @@ __global__ __launch_bounds__(kWG) void k_rotate_gram_small(RotArgs a, Small sm) 
 }
 
 __global__ __launch_bounds__(kWG) void k_scale(ScaleArgs a) {
+  if (a.stop && (a.stop->done != 0 || *a.status != AA_OK)) return;
   scale_body(a.in, a.out, a.n, a.R[a.kk + (size_t)a.kk * a.cap], blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(kWG) void k_history(HistArgs a, Small sm) {
+  if (aa_stopped(sm)) return;
   __shared__ double s_acc[kWaves * 2];
   lds_zero(s_acc, kWaves * 2);
   __syncthreads();
@@ -263,6 +285,16 @@ __global__ __launch_bounds__(kWG) void k_history(HistArgs a, Small sm) {
 }
 
 __global__ __launch_bounds__(kWG) void k_xupdate(XupdArgs a, Small sm) {
+  if (aa_stopped(sm)) {
+    // the iteration has ended: x_next = x, except in the step that broke down
+    // (breakdown latched, not yet recorded as the end), which returns G(x_i)
+    const double* src = sm.stop->done == 0 ? a.g : a.x;
+    if (a.x_next != src)
+      for (int64_t r = (int64_t)blockIdx.x * kWG + threadIdx.x; r < a.n;
+           r += (int64_t)gridDim.x * kWG)
+        a.x_next[r] = src[r];
+    return;
+  }
   __shared__ double s_g[kMaxCols];
   __shared__ int s_slot[kMaxCols];
   __shared__ double s_acc[kWaves];
@@ -271,6 +303,21 @@ __global__ __launch_bounds__(kWG) void k_xupdate(XupdArgs a, Small sm) {
   __syncthreads();
   xupdate_body(a, s_g, s_slot, blockIdx.x, gridDim.x, s_acc + (threadIdx.x >> 6));
   publish(sm, 1, s_acc, 1);
+}
+
+// Ends the iteration at the cap of aa_set_stop (if nothing ended it before)
+// and writes x_next = x.
+__global__ __launch_bounds__(kWG) void k_stop_cap(StopState* stop, int k, int m_i,
+                                                  const double* x, double* xn, int64_t n) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && stop->done == 0) {
+    stop->iter = stop->cur;
+    stop->k = k;
+    stop->m_i = m_i;
+    stop->done = AA_STOPPED_CAP;
+  }
+  if (xn != x)
+    for (int64_t r = (int64_t)blockIdx.x * kWG + threadIdx.x; r < n; r += (int64_t)gridDim.x * kWG)
+      xn[r] = x[r];
 }
 
 __global__ void k_init_small(Small sm) {
@@ -289,7 +336,16 @@ __global__ void k_init_small(Small sm) {
     sm.gamma[i] = 0.0;
   }
   if (blockIdx.x == 0 && threadIdx.x < S_COUNT) sm.scal[threadIdx.x] = 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *sm.status = AA_OK;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *sm.status = AA_OK;
+    if (sm.stop) {
+      sm.stop->done = 0;
+      sm.stop->k = 0;
+      sm.stop->m_i = 0;
+      sm.stop->iter = 0;
+      sm.stop->cur = 0;
+    }
+  }
 }
 
 __global__ void k_copy(double* dst, const double* src, int64_t n) {
@@ -620,6 +676,16 @@ hipError_t launch_probe(int reads, int writes, const double* src, int64_t ld, do
 hipError_t launch_init_small(const Small& sm, hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
   hipLaunchKernelGGL(k_init_small, dim3(8), dim3(kWG), 0, st, sm);
+  return hipGetLastError();
+}
+
+hipError_t launch_stop_cap(StopState* stop, int k, int m_i, const double* x, double* xn,
+                           int64_t n, hipStream_t st) {
+  (void)hipGetLastError();  // drop a stale error left by an earlier call
+  int64_t blocks = (n + kWG - 1) / kWG;
+  int grid = (int)(blocks < 1024 ? blocks : 1024);
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_stop_cap, dim3(grid), dim3(kWG), 0, st, stop, k, m_i, x, xn, n);
   return hipGetLastError();
 }
 

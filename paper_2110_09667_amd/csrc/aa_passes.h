@@ -55,7 +55,11 @@ __device__ inline void run_tail(const Small& sm, const Tail& t, const double* re
       const double nv = sqrt(red[t.idx]);
       if (tid == 0) {
         R[k + (size_t)k * cap] = nv;
-        if (!(nv > 0.0) || !isfinite(nv)) *sm.status = AA_EBREAKDOWN;
+        // breakdown: R_kk not above 64 eps times the column's norm (the
+        // column numerically in the span of the window), or non-finite
+        double col = nv * nv;
+        for (int j = 0; j < k; ++j) col += R[j + (size_t)k * cap] * R[j + (size_t)k * cap];
+        if (!(nv > kBreakdownRel * sqrt(col)) || !isfinite(nv)) *sm.status = AA_EBREAKDOWN;
       }
       if (t.rhs) {
         // c_k = q_k^T f = (w^T f) / R_kk; c_0..c_{k-1} were stashed in gamma
@@ -132,13 +136,31 @@ __device__ inline void run_tail(const Small& sm, const Tail& t, const double* re
       rhs_backsolve(sm, k, lane < k ? red[lane] : 0.0);
       break;
     case TAIL_RES:
-      if (tid == 0) sm.scal[S_RES] = red[0];
+      if (tid == 0) {
+        sm.scal[S_RES] = red[0];
+        // the stopping test at the start of this iteration (reading A2):
+        // the residual against ||f_0||, or the previous step's length
+        if (sm.stop && sm.stop->done == 0) {
+          const bool hit = t.stop_mode == kStopResidual
+                               ? sqrt(red[0]) <= t.stop_tol * sqrt(sm.scal[S_RES0])
+                               : (t.stop_mode == kStopStep && sqrt(sm.scal[S_STEP]) < t.stop_tol);
+          if (hit) {
+            sm.stop->iter = sm.stop->cur;
+            sm.stop->k = t.k;
+            sm.stop->m_i = t.m_i;
+            sm.stop->done = AA_STOPPED_TEST;
+          } else {
+            sm.stop->cur += 1;  // iteration cur proceeds; the next one is cur + 1
+          }
+        }
+      }
       break;
     case TAIL_FIRST:
       if (tid == 0) {
         sm.scal[S_RES] = red[0];
         sm.scal[S_RES0] = red[0];
         sm.scal[S_STEP] = red[1];
+        if (sm.stop) sm.stop->cur = 1;  // the next iteration is i = 1
       }
       break;
     case TAIL_STEP:
@@ -190,7 +212,10 @@ __device__ inline void run_tail(const Small& sm, const Tail& t, const double* re
         R[k + (size_t)k * cap] = rkk;
         sm.scal[S_RHO] = rho;
         sm.scal[S_RKK] = rkk;
-        if (!(rho2 > 0.0) || !isfinite(rho2) || !(w2 > 0.0) || !isfinite(w2))
+        // the squared norms carry rounding of order eps times the squared
+        // norm they are taken from: below 64 eps of it they are noise
+        if (!(rho2 > kBreakdownRel * red[k + p]) || !isfinite(rho2) ||
+            !(w2 > kBreakdownRel * red[t.idx]) || !isfinite(w2))
           *sm.status = AA_EBREAKDOWN;
         if (t.rhs) {
           // c = Q^T f of the grown basis from the same reduction: c_j = c'_j,

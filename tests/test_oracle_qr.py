@@ -284,3 +284,24 @@ def test_dcgs2_reorthogonalization_guard():
     q1 = g.Q[:, 1].copy()
     g.add(F[:, 2])
     assert not np.array_equal(g.Q[:, 1], q1)
+
+
+@pytest.mark.parametrize("variant", VARIANTS_ALL)
+def test_breakdown_on_a_repeated_column_only(variant):
+    """Reading A10: a column numerically in the span of the window (R_kk at
+    most 64 eps times its column norm) is a breakdown; a column 1e-9 away from
+    the span is not.  The lagged DCGS-2 takes the new column's norm from
+    Pythagoras, which resolves a distance above ~sqrt(eps) only (reading
+    A19): 1e-6 there."""
+    rng = np.random.default_rng(61)
+    n = 200
+    a, b = rng.standard_normal(n), rng.standard_normal(n)
+    q = O.QR(n, 3, variant)
+    assert q.add(a) == O.OK
+    assert q.add(a.copy()) == O.EBREAKDOWN
+    q2 = O.QR(n, 3, variant)
+    assert q2.add(a) == O.OK
+    d = 1e-6 if variant == "dcgs2_lag" else 1e-9
+    assert q2.add(a + d * b) == O.OK
+    R = q2.Rk()
+    assert R[1, 1] / np.linalg.norm(R[:, 1]) > d / 10
