@@ -210,6 +210,7 @@ aa_status aa_batch_init(aa_batch** out, int count, const aa_batch_instance* inst
     sm.status = (int*)(base + o); o = align_up(o + sizeof(int));
     sm.partials = nullptr;
     sm.cap = m;
+    sm.stop = nullptr;  // batched instances stop by their own per-instance test
     BState& st = hs[j];
     st.iter = 0; st.conv_iter = -1; st.k = 0; st.m_i = 0; st.active = 1; st.status = 0;
     st.res_norm = st.res0_norm = 0.0;
