@@ -433,50 +433,51 @@ def poisson1d_to_tolerance(variant, tol=1e-8, cap=300, check_every=1):
 
 def nonlinear3d_to_tolerance(prob, m, variant, tol=1e-8, cap=20000, check_every=10, flags=0):
     """The 3D nonlinear workload solved from u_0 = 0 to ||f_i|| <= tol ||f_0||
-    (or the cap) with the single-instance entry points, the stop test read
-    every ``check_every`` steps.  Returns iterations, wall seconds (G
-    evaluations included), the final relative residual and whether it
-    converged."""
+    (or the cap) with the single-instance entry points and the device-side
+    stop test (aa_set_stop), the host reading the state every
+    ``check_every`` steps (steps after the end return at once).  Returns
+    iterations, wall seconds (G evaluations included), the final relative
+    residual and whether it converged."""
     import torch
     from paper_2110_09667_amd import aa
     dev = torch.device("cuda:0")
     f_d = device_rhs(prob)
     ctx = aa.AAContext(prob.n, m, variant, flags)
+    ctx.set_stop(tol, cap)  # the stopping test runs on the device
     x = torch.zeros(prob.n, dtype=torch.float64, device=dev)
     g = torch.empty_like(x)
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
-    it = 0
-    info = None
-    while it < cap:
-        aa.aa_problem_apply(prob.d, prob.s, prob.h, prob.omega, prob.c, f_d, x, g)
-        ctx.step(x, g, x)
-        it += 1
-        if it % check_every == 0 or it == cap:
-            info = ctx.info()
-            if info.status != 0:
-                break
-            if info.iter > 1 and info.res_norm <= tol * info.res0_norm:
-                break
-    torch.cuda.synchronize(dev)
+    calls = 0
+    while True:
+        for _ in range(check_every):
+            aa.aa_problem_apply(prob.d, prob.s, prob.h, prob.omega, prob.c, f_d, x, g)
+            ctx.step(x, g, x)
+            calls += 1
+        info = ctx.info()
+        if info.stopped:
+            break
     wall = time.perf_counter() - t0
-    info = ctx.info()
     ctx.close()
     del f_d, x, g
     torch.cuda.empty_cache()
+    it = int(info.stop_iter)
     rel = info.res_norm / info.res0_norm
-    return {"iterations": it, "converged": bool(rel <= tol), "final_rel_residual": rel,
-            "wall_s": round(wall, 3), "ms_per_iter": round(1e3 * wall / max(it, 1), 4),
-            "status": int(info.status)}
+    return {"iterations": it, "converged": info.stopped == aa.STOPPED_TEST,
+            "final_rel_residual": rel, "wall_s": round(wall, 3),
+            "ms_per_iter": round(1e3 * wall / max(it, 1), 4), "status": int(info.status),
+            "stopped": int(info.stopped)}
 
 
 def em_to_tolerance(variant, flags=0, replicas=500_000, nsamples=100_000, m=3, tol=1e-8,
                     cap=100, reps=5):
     """The EM workload (Sec. 5.3): n = 3 x replicas (1.5 million, the paper's
     vector per GPU), 100,000 samples, m = 3, from the samples' 1/6, 1/2, 5/6
-    quantiles to ||f_i|| <= tol ||f_0||, the stop test read every step.
-    Returns the iterations and the best of ``reps`` wall times (G and AA),
-    with the time in G and in aa_step split by events."""
+    quantiles to ||f_i|| <= tol ||f_0|| with the library's device-side stop
+    test (aa_set_stop), the host reading the state every 4 steps.  Returns
+    the iterations and the best of ``reps`` wall times (G and AA, up to the
+    host seeing the end), with the time in G and in aa_step up to the end
+    split by events."""
     import numpy as np
     import torch
     import aa_workloads as W
@@ -489,34 +490,34 @@ def em_to_tolerance(variant, flags=0, replicas=500_000, nsamples=100_000, m=3, t
     best = None
     for _ in range(reps):
         ctx = aa.AAContext(prob.n, m, variant, flags)
+        ctx.set_stop(tol, cap)  # tested on the device: no per-step wait
         x = u0.clone()
         g = torch.empty_like(x)
         evs = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        its = 0
+        calls = 0
         while True:
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-            e[0].record(stream)
-            aa.aa_em_apply(prob.alpha, prob.sigma, xd, x, g, work)
-            e[1].record(stream)
-            if its >= 1:
-                info = ctx.info()
-                if info.res_norm <= tol * info.res0_norm or its >= cap:
-                    evs.append((e[0], e[1], None))
-                    break
-            ctx.step(x, g, x)
-            e[2].record(stream)
-            evs.append(tuple(e))
-            its += 1
-        torch.cuda.synchronize()
+            for _ in range(4):  # steps after the end return at once
+                e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+                e[0].record(stream)
+                aa.aa_em_apply(prob.alpha, prob.sigma, xd, x, g, work)
+                e[1].record(stream)
+                ctx.step(x, g, x)
+                e[2].record(stream)
+                evs.append(tuple(e))
+                calls += 1
+            info = ctx.info()
+            if info.stopped:
+                break
         wall = time.perf_counter() - t0
-        g_ms = sum(a.elapsed_time(b) for a, b, _ in evs)
-        aa_ms = sum(b.elapsed_time(c) for a, b, c in evs if c is not None)
-        info = ctx.info()
+        its = info.stop_iter  # x_its is the answer: its steps were taken
+        g_ms = sum(a.elapsed_time(b) for a, b, _ in evs[:its + 1])
+        aa_ms = sum(b.elapsed_time(c) for a, b, c in evs[:its])
         ctx.close()
-        r = {"iterations": its, "converged": bool(info.res_norm <= tol * info.res0_norm),
-             "wall_ms": round(1e3 * wall, 3), "g_ms": round(g_ms, 3), "aa_ms": round(aa_ms, 3)}
+        r = {"iterations": its, "converged": info.stopped == aa.STOPPED_TEST,
+             "wall_ms": round(1e3 * wall, 3), "g_ms": round(g_ms, 3), "aa_ms": round(aa_ms, 3),
+             "calls_enqueued": calls}
         if best is None or r["wall_ms"] < best["wall_ms"]:
             best = r
     best["n"] = prob.n
