@@ -379,6 +379,61 @@ def batched_run(probs, ms, variant, tol, cap, chunk, stream, net=None, steady=20
     return out
 
 
+def batched_tail(variant, takes=(8, 32, 128), fuse=0, steady=20):
+    """The tail of a batch: only the `take` largest instances of the batched
+    table still active.  Steady time per iteration with every instance in the
+    persistent kernel (one workgroup each) against the split path (each
+    instance on the grid-wide passes, one after another)."""
+    import torch
+    import aa_workloads as W
+    from paper_2110_09667_amd import aa
+    table = W.batch_table(4096)
+    order = sorted(range(len(table)), key=lambda j: (table[j].s * table[j].s * table[j].m, -j),
+                   reverse=True)
+    stream = torch.cuda.Stream()
+    out = {}
+    for take in takes:
+        insts = [table[j] for j in order[:take]]
+        probs = [BatchProblem2D(i) for i in insts]
+        ms = [i.m for i in insts]
+        vec = sum(batch_iter_vectors(variant, i.m, i.m, i.m - 1, fuse) * p.n
+                  for i, p in zip(insts, probs))
+        row = {"instances": take, "n_min": min(p.n for p in probs),
+               "n_max": max(p.n for p in probs)}
+        with torch.cuda.stream(stream):
+            for mode in ("persistent", "split"):
+                b = aa.AABatch(probs, ms, variant, flags=fuse, tol=0.0, max_iter=10**9,
+                               stream=stream)
+                b.set_split(1 if mode == "split" else 0, take)
+                b.run(21)   # every window full
+                b.run(1)    # the split policy applies at the start of a run
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                e0.record(stream)
+                b.run(steady)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                wall = (time.perf_counter() - t0) / steady
+                ms_it = e0.elapsed_time(e1) / steady
+                row[mode] = {"ms_per_iter": round(ms_it, 3),
+                             "host_ms_per_iter": round(1e3 * wall, 3),
+                             "algorithmic_gbs": round(8.0 * vec / (ms_it * 1e-3) / 1e9, 1),
+                             "split_instances": b.split_count()}
+                b.close()
+                del b
+        row["split_speedup"] = round(row["persistent"]["ms_per_iter"] /
+                                     row["split"]["ms_per_iter"], 2)
+        out[str(take)] = row
+        print(f"# batched tail, {take} largest instances: persistent "
+              f"{row['persistent']['ms_per_iter']:.2f} ms/iter, split "
+              f"{row['split']['ms_per_iter']:.2f} ms/iter", file=sys.stderr, flush=True)
+        del probs
+        torch.cuda.empty_cache()
+    return out
+
+
 def poisson1d_to_tolerance(variant, tol=1e-8, cap=300, check_every=1):
     """The 1D Poisson workload (n = 4096, m = 5) solved to ||f|| <= tol ||f_0||
     with the single-instance entry points (the one-workgroup step at this n),
@@ -1018,6 +1073,9 @@ def main():
                                 args.train_iters, args.single_sample,
                                 fuse=(aa.FUSE_RHS | aa.FUSE_DELETE)
                                 if args.batch_passes == "fused" else 0)
+        batched["tail_largest_instances"] = batched_tail(
+            args.variant, fuse=(aa.FUSE_RHS | aa.FUSE_DELETE)
+            if args.batch_passes == "fused" else 0)
 
     # the roofline of the headline add's dominant kernel: algorithmic bytes per
     # launch / its average launch duration (per-launch events on the

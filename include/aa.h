@@ -377,21 +377,48 @@ typedef struct {
   int order;         /* instance order chosen (as aa_batch_set_schedule)     */
   double ms_per_iter;/* its measured time per batched iteration              */
   int trials;        /* candidate schedules timed (0: taken from the cache)  */
+  int pairs;         /* tiles chosen: row pairs per lane (aa_batch_set_tiles)*/
 } aa_batch_schedule;
+
+/* Tiles of the persistent kernel's passes: each lane streams `pairs` pairs
+ * of consecutive rows per tile (2 or 4: tiles of 1024 or 2048 rows for the
+ * 256-thread workgroup; two builds of the kernel).  Default 4. */
+aa_status aa_batch_set_tiles(aa_batch *b, int pairs);
+
+/* Large instances on many workgroups.  The persistent kernel gives every
+ * instance one workgroup, which streams some 20 GB/s; while thousands are
+ * active that fills the chip, but once at most `active_max` instances are
+ * active (0: a quarter of the compute units) the active instances with
+ * n >= min_n leave the persistent kernel and run their iterations on the
+ * single-instance grid-wide passes (up to 1024 workgroups each), one
+ * instance after another, the remaining ones staying in the persistent
+ * kernel.  A split instance keeps its memory, its state and the batch's
+ * stopping test (relative residual, iteration cap); its partial sums are
+ * taken in another order (results agree to rounding), and a breakdown ends
+ * it in the iteration that detects it with x_{i+1} = G(x_i), as aa_step
+ * does.  The policy is evaluated when aa_batch_run starts (a wait for the
+ * stream); split iterations are enqueued by the host, not replayed as
+ * graphs; the learned entry points and the autotuner return every instance
+ * to the persistent kernel first.  min_n = 0 disables the split (and
+ * returns split instances).  Default: min_n = 65536, active_max = 0. */
+aa_status aa_batch_set_split(aa_batch *b, int64_t min_n, int active_max);
+
+/* Instances currently on the split path (as of the last aa_batch_run). */
+aa_status aa_batch_split_count(const aa_batch *b, int *count);
 
 /* Schedule autotuner (the batched path's tuning step; not in the paper).
  * Times `iters` real iterations of the batch under each candidate schedule
- * -- persistent workgroups in {1, 2, 3, 4} per compute unit (capped at the
- * instance count) x instance order {largest n*m first, as given} -- with
- * events on the batch's stream, and keeps the fastest (graph replay stays as
- * set).  The iterations it runs are ordinary progress of the batch, so call
- * it once the windows are full (after max m iterations) for a fair
- * comparison.  With cache_path non-NULL the result is looked up first in,
- * and afterwards appended to, a text file of lines
- * "<gcn arch> <workload signature> <grid> <order> <ms per iteration>"; the
- * signature hashes the variant, the flags and every instance's (n, m, dim).
- * A cache hit applies the stored schedule and runs nothing.  best may be
- * NULL.  Waits for the stream. */
+ * -- tiles {4, 2} row pairs per lane x persistent workgroups in {1, 2, 3, 4}
+ * per compute unit (capped at the instance count) x instance order {largest
+ * n*m first, as given} -- with events on the batch's stream, and keeps the
+ * fastest (graph replay stays as set).  The iterations it runs are ordinary
+ * progress of the batch, so call it once the windows are full (after max m
+ * iterations) for a fair comparison.  With cache_path non-NULL the result is
+ * looked up first in, and afterwards appended to, a text file of lines
+ * "<gcn arch> <workload signature> <grid> <order> <pairs> <ms per
+ * iteration>"; the signature hashes the format, the variant, the flags and
+ * every instance's (n, m, dim).  A cache hit applies the stored schedule and
+ * runs nothing.  best may be NULL.  Waits for the stream. */
 aa_status aa_batch_autotune(aa_batch *b, int iters, const char *cache_path,
                             aa_batch_schedule *best);
 

@@ -38,7 +38,8 @@ SYMBOLS = [
     "aa_mlp_get_params", "aa_mlp_get_grads", "aa_mlp_forward", "aa_mlp_backward",
     "aa_mlp_adam", "aa_mlp_destroy", "aa_batch_run_learned", "aa_batch_train",
     "aa_batch_read_learning", "aa_qr_solve_noalloc", "aa_bandwidth_probe", "aa_em_apply",
-    "aa_set_stop",
+    "aa_set_stop", "aa_batch_set_tiles", "aa_batch_set_split",
+    "aa_batch_split_count",
 ]
 EM_WORK_DOUBLES = 6144
 
@@ -77,7 +78,7 @@ class EmMixture(C.Structure):
 
 class BatchSchedule(C.Structure):
     _fields_ = [("grid", C.c_int), ("order", C.c_int), ("ms_per_iter", C.c_double),
-                ("trials", C.c_int)]
+                ("trials", C.c_int), ("pairs", C.c_int)]
 
 
 class BatchState(C.Structure):
@@ -108,6 +109,9 @@ def lib():
         "aa_step": [P, P, P, P],
         "aa_get_info": [P, C.POINTER(Info)],
         "aa_set_stop": [P, D, I64, I],
+        "aa_batch_set_tiles": [P, I],
+        "aa_batch_set_split": [P, I64, I],
+        "aa_batch_split_count": [P, C.POINTER(I)],
         "aa_qr_add": [P, P],
         "aa_qr_delete": [P],
         "aa_qr_solve": [P, P, P],
@@ -466,6 +470,22 @@ class AABatch:
 
     def set_schedule(self, grid: int = 0, order: int = 0, use_graph: bool = True):
         aa_batch_set_schedule(self.b, grid, order, use_graph)
+
+    def set_tiles(self, pairs: int):
+        """Row pairs per lane of the persistent kernel's tiles (2 or 4)."""
+        _check(lib().aa_batch_set_tiles(self.b, pairs), "aa_batch_set_tiles")
+
+    def set_split(self, min_n: int = 65536, active_max: int = 0):
+        """Move active instances with n >= min_n onto the grid-wide passes
+        once at most active_max are active (0: one per compute unit; min_n
+        = 0 never)."""
+        _check(lib().aa_batch_set_split(self.b, min_n, active_max), "aa_batch_set_split")
+
+    def split_count(self) -> int:
+        """Instances on the split path as of the last run."""
+        c = C.c_int(0)
+        _check(lib().aa_batch_split_count(self.b, C.byref(c)), "aa_batch_split_count")
+        return c.value
 
     def autotune(self, iters: int = 3, cache_path: str | None = None) -> "BatchSchedule":
         """Pick the persistent grid and instance order by timing real

@@ -576,6 +576,56 @@ void drop_graphs(aa_ctx* c) {
 
 }  // namespace
 
+namespace aa {
+
+aa_ctx* view_create(const BInst& I, int variant, unsigned flags, double* partials,
+                    StopState* stop, int64_t iter, int k, int m_i, double tol, int64_t max_iter,
+                    hipStream_t st) {
+  aa_ctx* c = new (std::nothrow) aa_ctx();
+  if (!c) return nullptr;
+  c->n = I.n;
+  c->ldq = I.ld;
+  c->m = I.m;
+  c->cap = I.m;
+  c->variant = variant;
+  c->flags = flags & ~(unsigned)AA_BATCH_LEARNED;
+  c->stream = st;
+  c->Q = I.Q;
+  c->ring = I.ring;
+  c->W = I.W;
+  c->f_prev = I.f_prev;
+  c->g_prev = I.g_prev;
+  c->sm = I.sm;
+  c->sm.partials = partials;
+  c->sm.stop = nullptr;
+  c->stop_dev = stop;
+  c->one_wg_ok = false;
+  c->fused_max = 0;
+  c->iter = iter;
+  c->k = k;
+  c->m_i = m_i;
+  c->stop_mode = tol > 0.0 ? kStopResidual : kStopNone;
+  c->stop_tol = tol > 0.0 ? tol : 0.0;
+  // the batch stops at the start of iteration max_iter; aa_step's cap lets
+  // iterations up to c->max_iter run
+  c->max_iter = max_iter > 1 ? max_iter - 1 : 1;
+  return c;
+}
+
+void view_counters(const aa_ctx* c, int64_t* iter, int* k, int* m_i) {
+  *iter = c->iter;
+  *k = c->k;
+  *m_i = c->m_i;
+}
+
+void view_destroy(aa_ctx* c) {
+  if (!c) return;
+  drop_graphs(c);
+  delete c;
+}
+
+}  // namespace aa
+
 extern "C" {
 
 aa_status aa_workspace_size(int64_t n, int m, int variant, unsigned flags, size_t* bytes) {

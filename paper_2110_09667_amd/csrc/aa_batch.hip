@@ -21,12 +21,25 @@
 // two took the one-instance step from 84 to 77 us (n = 4096, m = 5) and from
 // 654 to 564 us (n = 13824, m = 20).  Only device code sees the value (no
 // host code shares it), so the two translation units may differ.
+//
+// The file is compiled twice: as itself (four row pairs, namespace aa::p4,
+// with the host helpers), and through aa_batch_p2.hip with two row pairs
+// (namespace aa::p2, AA_BATCH_SECONDARY): the batch schedule autotuner
+// chooses the tiling at run time.
 #ifndef AA_PAIRS
 #define AA_PAIRS 4
+#endif
+#ifndef AA_BATCH_SECONDARY
+#define AA_BATCH_SECONDARY 0
 #endif
 #include "aa_passes.h"
 
 namespace aa {
+#if AA_BATCH_SECONDARY
+namespace p2 {
+#else
+namespace p4 {
+#endif
 
 __device__ __forceinline__ Tail mk_tail(int op, int k) {
   Tail t{};
@@ -732,6 +745,7 @@ __global__ __launch_bounds__(kWG, 2) void k_batch(BatchArgs b) {
     __syncthreads();
     if (idx >= b.count) break;
     const int j = b.order[idx];
+    if (b.skip && b.skip[j]) continue;  // on the grid-wide passes this iteration
     const BState st = b.state[j];
     if (!st.active && !st.pending) {
       if (b.mode == BM_PHASE_A) write_features(b.inst[j], st, b.feat + (size_t)j * kFeat, false);
@@ -794,6 +808,9 @@ hipError_t launch_batch(const BatchArgs& b, int grid, int kbucket, bool gram, in
               : launch_kb<false>(b, grid, kbucket, lds, st);
 }
 
+}  // namespace p2 / p4
+
+#if !AA_BATCH_SECONDARY
 bool batch_needs_gram(int variant, unsigned flags) {
   return variant == AA_ICWY || ((flags & AA_FUSE_DELETE) && variant != AA_MGS);
 }
@@ -810,14 +827,21 @@ int batch_stage_cols(int mmax, int variant, unsigned flags) {
 
 hipError_t launch_batch_init(BInst* inst, int count, hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
-  hipLaunchKernelGGL(k_batch_init, dim3(count), dim3(kWG), 0, st, inst, count);
+  hipLaunchKernelGGL(p4::k_batch_init, dim3(count), dim3(kWG), 0, st, inst, count);
   return hipGetLastError();
 }
 
 hipError_t launch_batch_reset(unsigned* counter, hipStream_t st) {
   (void)hipGetLastError();  // drop a stale error left by an earlier call
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, counter);
+  hipLaunchKernelGGL(p4::k_batch_reset, dim3(1), dim3(64), 0, st, counter);
   return hipGetLastError();
 }
+
+hipError_t launch_batch(const BatchArgs& b, int grid, int kbucket, bool gram, int stage_cols,
+                        hipStream_t st, int pairs) {
+  return pairs == 2 ? p2::launch_batch(b, grid, kbucket, gram, stage_cols, st)
+                    : p4::launch_batch(b, grid, kbucket, gram, stage_cols, st);
+}
+#endif
 
 }  // namespace aa

@@ -241,6 +241,8 @@ struct BatchArgs {
   const double* ox; const double* og; double* oxn;
   int64_t ov_iter; int ov_k;
   int mode;               // BatchMode
+  const int* skip;        // plain mode: instances the persistent kernel leaves out
+                          // (advanced on the grid-wide passes instead); may be null
   int stop_mode;          // fused single-instance step: the stopping test
   double stop_tol;
   float* feat;            // [count x kFeat] network inputs (phase A)
@@ -251,8 +253,18 @@ struct BatchArgs {
 
 // stage_cols: largest number of columns the Gram staging holds (0: none);
 // dynamic LDS = max(kbucket^2, gram_lds_doubles(stage_cols)) doubles.
+// pairs: row pairs per lane per tile of the batched kernel's passes (4 or 2:
+// two builds of aa_batch.hip, the autotuner's tile dimension)
+hipError_t launch_batch(const BatchArgs&, int grid, int kbucket, bool gram, int stage_cols,
+                        hipStream_t, int pairs = 4);
+namespace p4 {
 hipError_t launch_batch(const BatchArgs&, int grid, int kbucket, bool gram, int stage_cols,
                         hipStream_t);
+}
+namespace p2 {
+hipError_t launch_batch(const BatchArgs&, int grid, int kbucket, bool gram, int stage_cols,
+                        hipStream_t);
+}
 // Staged Gram columns and whether the batched kernel needs its Gram
 // instantiation, for a window of up to mmax columns, variant and flags.
 int batch_stage_cols(int mmax, int variant, unsigned flags);
@@ -260,6 +272,22 @@ bool batch_needs_gram(int variant, unsigned flags);
 hipStream_t mlp_stream(const aa_mlp*);
 int mlp_max_batch(const aa_mlp*);
 hipError_t launch_batch_reset(unsigned* counter, hipStream_t);
+
+// A single-instance context over a batched instance's memory (Q, history,
+// small block), with a shared partials buffer and its own stop state: the
+// batch's split path runs a large instance's iterations on the grid-wide
+// passes.  Counters are the instance's (iteration, columns, window); tol and
+// max_iter the batch's (the instance stops at the start of iteration i with
+// ||f_i|| <= tol ||f_0|| or i >= max_iter).
+aa_ctx* view_create(const BInst& I, int variant, unsigned flags, double* partials,
+                    StopState* stop, int64_t iter, int k, int m_i, double tol, int64_t max_iter,
+                    hipStream_t st);
+void view_counters(const aa_ctx* c, int64_t* iter, int* k, int* m_i);
+void view_destroy(aa_ctx* c);
+hipError_t launch_set_int(int* p, int64_t n, int v, hipStream_t);
+// The batched state of a split instance from its stop state and small block.
+hipError_t launch_split_state(BState* st, const StopState* stop, const Small& sm, int k, int m_i,
+                              hipStream_t);
 hipError_t launch_batch_init(BInst* inst, int count, hipStream_t);
 
 // launchers (aa_kernels.hip)

@@ -305,6 +305,56 @@ __global__ __launch_bounds__(kWG) void k_xupdate(XupdArgs a, Small sm) {
   publish(sm, 1, s_acc, 1);
 }
 
+// The batched state of an instance advanced on the grid-wide passes: its
+// next iteration, columns, window and residual while it runs; its stopping
+// iteration once its stop state has ended it (the batch's convention: the
+// iteration at whose start the test held is not counted as run).  G
+// evaluations: G(x_0) plus one per iteration begun.
+__global__ void k_split_state(BState* st, const StopState* stop, const double* scal,
+                              const int* status, int k, int m_i) {
+  if (threadIdx.x != 0) return;
+  BState s = *st;
+  s.res_norm = sqrt(scal[S_RES]);
+  s.status = *status;
+  if (stop->done) {
+    s.active = 0;
+    s.iter = stop->iter;
+    if (s.conv_iter < 0) s.conv_iter = stop->iter;
+    s.k = stop->k;
+    s.m_i = stop->m_i;
+    s.g_evals = stop->iter + 1;
+  } else {
+    s.iter = stop->cur;
+    s.k = k;
+    s.m_i = m_i;
+    s.g_evals = stop->cur;
+  }
+  *st = s;
+}
+
+__global__ void k_set_int(int* p, int64_t n, int v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_set_int(int* p, int64_t n, int v, hipStream_t st) {
+  (void)hipGetLastError();  // drop a stale error left by an earlier call
+  int64_t blocks = (n + 255) / 256;
+  int grid = (int)(blocks < 1024 ? blocks : 1024);
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_set_int, dim3(grid), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_state(BState* st, const StopState* stop, const Small& sm, int k, int m_i,
+                              hipStream_t s) {
+  (void)hipGetLastError();  // drop a stale error left by an earlier call
+  hipLaunchKernelGGL(k_split_state, dim3(1), dim3(64), 0, s, st, stop, sm.scal, sm.status, k,
+                     m_i);
+  return hipGetLastError();
+}
+
 // Ends the iteration at the cap of aa_set_stop (if nothing ended it before)
 // and writes x_next = x.
 __global__ __launch_bounds__(kWG) void k_stop_cap(StopState* stop, int k, int m_i,

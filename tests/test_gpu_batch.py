@@ -142,9 +142,10 @@ def test_batch_mixed_sizes_with_a_large_instance():
 
 def test_autotune_keeps_results_and_caches(tmp_path):
     """The autotuner runs real iterations under each candidate schedule: the
-    iterates equal those of an untuned batch after the same number of
-    iterations; a second tuning with the same cache file runs no trial and
-    applies the stored schedule."""
+    iterates match those of an untuned batch after the same number of
+    iterations (to rounding: the tiling sets the order of the partial sums);
+    a second tuning with the same cache file runs no trial and applies the
+    stored schedule."""
     import torch
     device()
     from paper_2110_09667_amd import aa
@@ -165,13 +166,14 @@ def test_autotune_keeps_results_and_caches(tmp_path):
         sp, _ = bp.read()
         for j in range(len(insts)):
             assert st[j].iter == sp[j].iter == done
-            assert np.array_equal(bt.x[j].cpu().numpy(), bp.x[j].cpu().numpy())
+            assert rel(bt.x[j].cpu().numpy(), bp.x[j].cpu().numpy()) <= 1e-10
         again = bp.autotune(2, cache)
         assert again.trials == 0 and again.grid == best.grid and again.order == best.order
+        assert again.pairs == best.pairs in (2, 4)
         assert bp.read()[0][0].iter == done
     with open(cache) as fh:
         lines = fh.read().split()
-    assert len(lines) == 5 and lines[0].startswith("gfx")
+    assert len(lines) == 6 and lines[0].startswith("gfx")
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
