@@ -747,15 +747,19 @@ def cpu_baseline(n=1 << 22, k=19, variant="icwy", reps=5):
     q = O.QR(n, k + 1, variant)
     for j in range(k):
         q.add(W.normal(W.SEED_QR_Q, j, n))
-    v = W.normal(W.SEED_QR_V, 0, n)
     u = 8.0 * n
     vecs = {"mgs": 4 * k + 3, "cgs2": 3 * k + 6, "dcgs2": 2 * k + 6, "icwy": 2 * k + 5,
             "dcgs2_lag": 2 * k + 4}[variant]
     res = {}
+    cycle = 0
     for threads in (1, allc):
         used = O.use_openmp(threads)
         ts = []
         for _ in range(reps):
+            # a fresh column every cycle: the delete drops the oldest column,
+            # so the last v stays in the basis
+            v = W.normal(W.SEED_QR_V, cycle, n)
+            cycle += 1
             t0 = time.perf_counter()
             assert q.add(v) == O.OK
             ts.append(time.perf_counter() - t0)

@@ -24,3 +24,14 @@ def test_help_lists_the_measurement_modes():
     for flag in ("--steps", "--warmup", "--gpus", "--c2-to-tol", "--poisson-only",
                  "--batch-cap", "--copy-calibration", "--qr-micro-only"):
         assert flag in r.stdout, flag
+
+
+def test_cpu_baseline_leg_runs_on_a_small_sample():
+    """The CPU-baseline leg (the oracle timed on the host) on a small basis:
+    every add of its timing loop must be accepted (each cycle adds a fresh
+    column, since the delete drops the oldest one)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    out = bench.cpu_baseline(n=1 << 12, k=5, reps=3)
+    assert out["kind"] == "oracle" and out["value"] > 0 and out["one_core_value"] > 0
+    assert out["cores"] >= 1
