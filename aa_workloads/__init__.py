@@ -208,3 +208,78 @@ def em_problem(nsamples: int = 100_000, replicas: int = 500_000, seed: int = SEE
     x = np.asarray(mu)[comp] + np.asarray(sigma)[comp] * z
     return EMProblem(samples=x, alpha=tuple(alpha), sigma=tuple(sigma), mu_true=tuple(mu),
                      replicas=replicas)
+
+
+# --------------------------------------------------------------------------
+# 2D heat equation with a nonlinear term (Sec. 5.1) and the 2D Bratu problem
+# (Sec. 5.2) on the unit square: N x N interior points (x fastest),
+# h = 1 / (N + 1), zero Dirichlet values.  This module only tabulates the
+# source term of the manufactured solution; the fixed-point maps (a linear
+# Poisson solve per evaluation) live in the oracle and in the library.
+# --------------------------------------------------------------------------
+
+PDE_HEAT_NL1, PDE_HEAT_NL2, PDE_BRATU = 1, 2, 3
+
+
+@dataclass
+class PDE2DProblem:
+    problem: int                 # PDE_HEAT_NL1, PDE_HEAT_NL2 or PDE_BRATU
+    N: int                       # interior points per side; n = N * N
+    m: int                       # window the paper uses for this problem
+    b: np.ndarray | None = None  # heat: f at the grid points (None for Bratu)
+    lam: float = 6.7             # Bratu parameter
+    tol: float = 1e-10           # nonlinear and linear tolerance of the paper
+
+    @property
+    def n(self) -> int:
+        return self.N * self.N
+
+    @property
+    def h(self) -> float:
+        return 1.0 / (self.N + 1)
+
+    def u0(self) -> np.ndarray:
+        return np.zeros(self.n)
+
+
+def grid_points(N: int):
+    """Coordinates (X, Y) of the interior points, (N, N) arrays, x fastest."""
+    t = np.arange(1, N + 1, dtype=np.float64) / (N + 1)
+    return np.meshgrid(t, t, indexing="xy")
+
+
+def heat_exact(N: int) -> np.ndarray:
+    """u(x, y) = sin^2(pi x) sin^2(pi y) at the interior points (flat)."""
+    X, Y = grid_points(N)
+    return (np.sin(np.pi * X) ** 2 * np.sin(np.pi * Y) ** 2).reshape(-1)
+
+
+def heat_source(N: int, term: int) -> np.ndarray:
+    """f = u_xx + u_yy + c(u) of the manufactured solution u = sin^2(pi x)
+    sin^2(pi y), evaluated at the grid points (flat): the two second
+    derivatives 2 pi^2 (cos^2 - sin^2) times the other factor, and the
+    reaction term of the chosen problem at u."""
+    X, Y = grid_points(N)
+    sx, cx = np.sin(np.pi * X), np.cos(np.pi * X)
+    sy, cy = np.sin(np.pi * Y), np.cos(np.pi * Y)
+    lap = 2 * np.pi ** 2 * (cx * cx - sx * sx) * sy * sy + 2 * np.pi ** 2 * (cy * cy - sy * sy) * sx * sx
+    u = sx * sx * sy * sy
+    if term == PDE_HEAT_NL1:
+        eu = np.exp(u)
+        cu = u + u * eu + u * np.exp(-u) + (u - eu) ** 2
+    elif term == PDE_HEAT_NL2:
+        cu = 100.0 * (u - u * u)
+    else:
+        raise ValueError(term)
+    return (lap + cu).reshape(-1)
+
+
+def heat2d(N: int = 1024, term: int = PDE_HEAT_NL1) -> PDE2DProblem:
+    """Sec. 5.1 on a 1024 x 1024 grid: term 1 with m = 5, term 2 with m = 10."""
+    return PDE2DProblem(problem=term, N=N, m=5 if term == PDE_HEAT_NL1 else 10,
+                        b=heat_source(N, term))
+
+
+def bratu2d(N: int = 1024, lam: float = 6.7) -> PDE2DProblem:
+    """Sec. 5.2 on a 1024 x 1024 grid, lambda = 6.7, m = 30."""
+    return PDE2DProblem(problem=PDE_BRATU, N=N, m=30, lam=lam)
