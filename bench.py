@@ -266,11 +266,9 @@ def ceilings(n=1 << 26, reps=10):
     import numpy as np
     import torch
     from paper_2110_09667_amd import aa
-    # the library's column stride: n rounded up to 64, plus 64 at a power of
-    # two (vectors starting on the same HBM channel slow multi-vector streams)
+    # the library's column stride for long columns: 1024 (mod 2048) doubles
     ld = (n + 63) // 64 * 64
-    if ld & (ld - 1) == 0 or ld % 4096 == 0:
-        ld += 64
+    ld = (ld + 2047) // 2048 * 2048 + 1024
     src = torch.ones(8 * ld, dtype=torch.float64, device="cuda:0")
     dst = torch.empty(2 * ld, dtype=torch.float64, device="cuda:0")
     sink = torch.empty(4096, dtype=torch.float64, device="cuda:0")
