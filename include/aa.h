@@ -520,6 +520,56 @@ aa_status aa_em_apply(const aa_em_mixture *h_mix, const double *d_x, int64_t nsa
                       const double *d_u, double *d_out, int64_t n, double *d_work,
                       void *stream);
 
+/* The fixed-point maps of the paper's 2D test problems on the unit square,
+ * N x N interior points (x fastest, h = 1 / (N + 1)), zero Dirichlet values:
+ *   AA_PDE_HEAT_NL1, AA_PDE_HEAT_NL2 -- the steady heat equation with a
+ *     nonlinear term of Sec. 5.1, u_xx + u_yy + c(u) = f with
+ *     c(u) = u + u e^u + u e^-u + (u - e^u)^2 (term 1) or 100 (u - u^2)
+ *     (term 2); G(u) = A^{-1}(c(u) - b), b = f at the grid points;
+ *   AA_PDE_BRATU -- the Bratu problem of Sec. 5.2, u_xx + u_yy + lambda e^u
+ *     = 0; G(u) = A^{-1}(lambda e^u);
+ * A = -L_h, L_h the 5-point Laplacian (second-order centred differences).
+ * Each evaluation solves A x = rhs by the conjugate gradient preconditioned
+ * with one geometric-multigrid V(1,1) cycle (the paper uses a structured
+ * multigrid preconditioner of an external library; this one is the
+ * library's own): red-black Gauss-Seidel, red then black before the coarse
+ * correction and black then red after it, full weighting, bilinear
+ * interpolation, coarse point I at fine point 2 I + 1, coarse levels the
+ * 5-point operator at spacing 2^l h whose last row and column keep the
+ * boundary at its true distance (diagonal (1 + 2^l) / H^2 from that side:
+ * the 1D Galerkin products).  The grid halves while N is even; the sizes must
+ * reach one of at most 32 (N = a 2^j with odd a <= 32, N <= 65536), else
+ * AA_EINVAL.  The solve starts from x = 0 and stops before iteration k when
+ * ||r_k||_2 <= tol ||rhs||_2, or at max_iter (not converged: see
+ * aa_pde2d_last).  The stopping test runs on the device; the host reads the
+ * solve's state after a batch of iterations sized by the previous solve, so
+ * aa_pde2d_apply and aa_pde2d_solve return after the stream has reached
+ * the end of the solve (they synchronize `stream`).
+ *
+ * Workspace: caller-owned device memory of aa_pde2d_workspace_size bytes,
+ * 256-byte aligned (about 7 N^2 doubles), kept alive until
+ * aa_pde2d_destroy; the context is a small host allocation.  One context
+ * per stream; calls on one context must not overlap. */
+typedef struct aa_pde2d aa_pde2d;
+enum { AA_PDE_HEAT_NL1 = 1, AA_PDE_HEAT_NL2 = 2, AA_PDE_BRATU = 3 };
+aa_status aa_pde2d_workspace_size(int64_t N, int max_iter, size_t *bytes);
+aa_status aa_pde2d_init(aa_pde2d **ctx, int64_t N, int problem, double lambda, double tol,
+                        int max_iter, void *d_workspace, size_t bytes, void *stream);
+/* d_out = G(d_u); d_b: the heat problems' source f at the grid points (N^2
+ * doubles; ignored and may be null for Bratu).  d_out may alias d_u. */
+aa_status aa_pde2d_apply(aa_pde2d *ctx, const double *d_b, const double *d_u, double *d_out);
+/* d_x = A^{-1} d_rhs by the same PCG (d_x must not alias d_rhs). */
+aa_status aa_pde2d_solve(aa_pde2d *ctx, const double *d_rhs, double *d_x);
+/* d_z = B d_r, one V-cycle (the preconditioner) on the fine grid; async. */
+aa_status aa_pde2d_vcycle(aa_pde2d *ctx, const double *d_r, double *d_z);
+/* iters >= 0: every later solve runs exactly that many PCG iterations
+ * (<= max_iter) regardless of the tolerance; -1 restores the test. */
+aa_status aa_pde2d_set_iters(aa_pde2d *ctx, int iters);
+/* PCG iterations of the last solve and whether it met the tolerance. */
+aa_status aa_pde2d_last(const aa_pde2d *ctx, int *h_iters, int *h_converged);
+aa_status aa_pde2d_set_stream(aa_pde2d *ctx, void *stream);
+aa_status aa_pde2d_destroy(aa_pde2d *ctx);
+
 /* Measurement: the sustained HBM bandwidth of an access pattern, with the
  * streaming passes' tiles, loads, stores and launch shape (at most 1024
  * workgroups, one resident round).  Reads `reads` vectors of length n from

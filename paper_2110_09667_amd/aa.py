@@ -39,8 +39,11 @@ SYMBOLS = [
     "aa_mlp_adam", "aa_mlp_destroy", "aa_batch_run_learned", "aa_batch_train",
     "aa_batch_read_learning", "aa_qr_solve_noalloc", "aa_bandwidth_probe", "aa_em_apply",
     "aa_set_stop", "aa_batch_set_tiles", "aa_batch_set_split",
-    "aa_batch_split_count",
+    "aa_batch_split_count", "aa_pde2d_workspace_size", "aa_pde2d_init", "aa_pde2d_apply",
+    "aa_pde2d_solve", "aa_pde2d_vcycle", "aa_pde2d_set_iters", "aa_pde2d_last",
+    "aa_pde2d_set_stream", "aa_pde2d_destroy",
 ]
+PDE_HEAT_NL1, PDE_HEAT_NL2, PDE_BRATU = 1, 2, 3
 EM_WORK_DOUBLES = 6144
 
 BATCH_LEARNED = 1 << 9
@@ -154,6 +157,15 @@ def lib():
         "aa_batch_run_learned": [P, P, I],
         "aa_batch_train": [P, P, I, C.c_float],
         "aa_batch_read_learning": [P, P, P, P],
+        "aa_pde2d_workspace_size": [I64, I, C.POINTER(C.c_size_t)],
+        "aa_pde2d_init": [C.POINTER(P), I64, I, D, D, I, P, C.c_size_t, P],
+        "aa_pde2d_apply": [P, P, P, P],
+        "aa_pde2d_solve": [P, P, P],
+        "aa_pde2d_vcycle": [P, P, P],
+        "aa_pde2d_set_iters": [P, I],
+        "aa_pde2d_last": [P, C.POINTER(I), C.POINTER(I)],
+        "aa_pde2d_set_stream": [P, P],
+        "aa_pde2d_destroy": [P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -223,6 +235,50 @@ def aa_qr_solve(ctx, f, gamma):
 def aa_bandwidth_probe(reads, writes, src, ld, dst, n, sink, stream=None):
     _check(lib().aa_bandwidth_probe(reads, writes, _ptr(src), ld, _ptr(dst), n, _ptr(sink),
                                     _stream(stream)), "aa_bandwidth_probe")
+
+
+def aa_pde2d_workspace_size(N: int, max_iter: int) -> int:
+    b = C.c_size_t(0)
+    _check(lib().aa_pde2d_workspace_size(N, max_iter, C.byref(b)), "aa_pde2d_workspace_size")
+    return b.value
+
+
+def aa_pde2d_init(N, problem, lam, tol, max_iter, workspace, stream=None):
+    ctx = C.c_void_p()
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(lib().aa_pde2d_init(C.byref(ctx), N, problem, lam, tol, max_iter,
+                               workspace.data_ptr(), nbytes, _stream(stream)), "aa_pde2d_init")
+    return ctx
+
+
+def aa_pde2d_apply(ctx, b, u, out):
+    _check(lib().aa_pde2d_apply(ctx, _ptr(b), _ptr(u), _ptr(out)), "aa_pde2d_apply")
+
+
+def aa_pde2d_solve(ctx, rhs, x):
+    _check(lib().aa_pde2d_solve(ctx, _ptr(rhs), _ptr(x)), "aa_pde2d_solve")
+
+
+def aa_pde2d_vcycle(ctx, r, z):
+    _check(lib().aa_pde2d_vcycle(ctx, _ptr(r), _ptr(z)), "aa_pde2d_vcycle")
+
+
+def aa_pde2d_set_iters(ctx, iters: int):
+    _check(lib().aa_pde2d_set_iters(ctx, iters), "aa_pde2d_set_iters")
+
+
+def aa_pde2d_last(ctx):
+    it, conv = C.c_int(0), C.c_int(0)
+    _check(lib().aa_pde2d_last(ctx, C.byref(it), C.byref(conv)), "aa_pde2d_last")
+    return it.value, bool(conv.value)
+
+
+def aa_pde2d_set_stream(ctx, stream=None):
+    _check(lib().aa_pde2d_set_stream(ctx, _stream(stream)), "aa_pde2d_set_stream")
+
+
+def aa_pde2d_destroy(ctx):
+    _check(lib().aa_pde2d_destroy(ctx), "aa_pde2d_destroy")
 
 
 def aa_em_apply(alpha, sigma, x, u, out, work, stream=None):
@@ -581,3 +637,37 @@ class AAMlp:
             self.close()
         except Exception:
             pass
+
+class PDE2D:
+    """Owns a torch workspace and a library context of the 2D test problems'
+    map (Sec. 5.1, 5.2): G(u) by PCG with the library's multigrid cycle."""
+
+    def __init__(self, N: int, problem: int, lam: float = 6.7, tol: float = 1e-10,
+                 max_iter: int = 200, device="cuda", stream=None):
+        import torch
+        self.N, self.problem = int(N), int(problem)
+        nbytes = aa_pde2d_workspace_size(self.N, max_iter)
+        self.workspace = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=device)
+        assert self.workspace.data_ptr() % 256 == 0
+        self.ctx = aa_pde2d_init(self.N, self.problem, lam, tol, max_iter, self.workspace, stream)
+
+    def apply(self, b, u, out):
+        aa_pde2d_apply(self.ctx, b, u, out)
+
+    def solve(self, rhs, x):
+        aa_pde2d_solve(self.ctx, rhs, x)
+
+    def vcycle(self, r, z):
+        aa_pde2d_vcycle(self.ctx, r, z)
+
+    def set_iters(self, iters: int):
+        aa_pde2d_set_iters(self.ctx, iters)
+
+    def last(self):
+        return aa_pde2d_last(self.ctx)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and _lib is not None:
+            _lib.aa_pde2d_destroy(ctx)
+            self.ctx = None
