@@ -523,7 +523,7 @@ __device__ inline void update_body(const UpdArgs& a, const double* s_c1, const d
         o[i].y = (o[i].y - acc1[i].y) - acc2[i].y;
       }
     }
-    if (a.out) st2<F>(o, a.out, b2, a.n);
+    if (a.out) st2<F, AA_NT_STORE_UPDATE != 0>(o, a.out, b2, a.n);
     if (a.dotcol >= 0) sdot += dot2(dq, o);
     if (a.nrm) snrm += dot2(o, o);
     if (a.rhsv) {
@@ -1202,7 +1202,14 @@ __device__ inline void scale_body(const double* in, double* out, int64_t n, doub
   double2* out2 = reinterpret_cast<double2*>(out);
   for (int64_t r = t0 * kWG + threadIdx.x; r < npair; r += ts * kWG) {
     const f64x2 v = ld2v(in2 + r);
+#if AA_NT_STORE
+    f64x2 o;
+    o.x = v.x / d;
+    o.y = v.y / d;
+    __builtin_nontemporal_store(o, reinterpret_cast<f64x2*>(out2 + r));
+#else
     out2[r] = make_double2(v.x / d, v.y / d);
+#endif
   }
   if (t0 == 0 && threadIdx.x == 0 && (n & 1)) out[n - 1] = in[n - 1] / d;
 }

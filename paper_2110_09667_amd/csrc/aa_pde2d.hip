@@ -35,7 +35,7 @@ namespace aa {
 namespace pde {
 
 constexpr int kBX = 256;           // threads per workgroup of the grid-wide kernels
-constexpr int kMaxWG = 4096;       // workgroups of a grid-wide kernel (partials)
+constexpr int kMaxWG = 1024;       // workgroups of a grid-wide kernel (partials)
 constexpr int kCoarseN = 32;       // levels of at most this many points per side in LDS
 constexpr int kCoarseWG = 1024;    // threads of the coarse kernel
 constexpr int kCoarseLds = 3 * (1024 + 256 + 64 + 16 + 4 + 1);

@@ -87,6 +87,11 @@ hipError_t launch_stencil(int dim, int64_t s, double h, double omega, double c,
   return hipGetLastError();
 }
 
+// The generators write far more than the caches hold and nothing reads it back
+// at once: non-temporal stores.  (Ordinary stores leave the caches full of
+// dirty lines, and the next kernel's reads then share HBM with their write-
+// back: a 20-vector read pass ran 12 % slower right after a 512 MiB fill.)
+
 // counter origin of stream (seed, stream_id)
 static uint64_t stream_base(uint64_t seed, uint64_t stream_id) {
   return sm64_mix_host(sm64_mix_host(seed) + stream_id);
@@ -95,13 +100,13 @@ static uint64_t stream_base(uint64_t seed, uint64_t stream_id) {
 __global__ void k_fill_uniform(double* out, int64_t n, uint64_t base, double lo, double hi) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    out[i] = lo + (hi - lo) * u01(base + (uint64_t)i);
+    __builtin_nontemporal_store(lo + (hi - lo) * u01(base + (uint64_t)i), out + i);
 }
 
 __global__ void k_fill_normal(double* out, int64_t n, uint64_t base, uint64_t offset) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    out[i] = normal_at(base, offset + (uint64_t)i);
+    __builtin_nontemporal_store(normal_at(base, offset + (uint64_t)i), out + i);
 }
 
 // ---------------------------------------------------------------------------
