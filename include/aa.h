@@ -227,7 +227,7 @@ aa_status aa_qr_solve(aa_ctx *ctx, const double *d_f, double *d_gamma);
  * dimension ldr >= k, nonsingular (device); d_f: n doubles (device); d_gamma:
  * k doubles out (device).  1 <= k <= 64, else AA_EINVAL.  Asynchronous on
  * `stream`.  Allocates nothing: the reduction partials live in a fixed
- * 513 KiB device array that every GPU the library runs on keeps until the
+ * 257 KiB device array that every GPU the library runs on keeps until the
  * process ends, shared by all calls on that GPU -- calls that overlap on one
  * GPU (other streams, other host threads) race and must be serialized by the
  * caller. */
@@ -294,7 +294,7 @@ aa_status aa_profile_read(aa_ctx *ctx, int kind, double *ms, int64_t *launches,
 aa_status aa_profile_reset(aa_ctx *ctx);
 
 /* Upper bounds on the workgroups of the streaming passes and of the ICWY
- * Gram pass (defaults 1024 and 1024; each in [1, 4096]; the Gram pass also
+ * Gram pass (defaults 512 and 1024; each in [1, 4096]; the Gram pass also
  * keeps (workgroups) x (k-1)(k-2)/2 within its partials buffer).  A pass is
  * further limited to the workgroups of its kernel that the device holds at
  * once (one round), as the occupancy query reports. */

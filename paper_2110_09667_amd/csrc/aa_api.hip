@@ -26,7 +26,10 @@ struct aa_ctx {
   double* f_prev = nullptr; // ldq, AA only
   double* g_prev = nullptr; // ldq, AA only
   Small sm{};
-  int grid_stream_max = 1024;  // workgroups of the streaming passes
+  // workgroups of the streaming passes: two per compute unit (measured at n =
+  // 2^26 and the 256^3 step against 768 and 1024: 1-2 % faster; with four per
+  // CU the update pass runs at 5.47 TB/s, with two at 5.62)
+  int grid_stream_max = 512;
   int grid_gram_max = 1024;    // workgroups of the ICWY Gram pass
   int64_t iter = 0;
   int k = 0, m_i = 0;

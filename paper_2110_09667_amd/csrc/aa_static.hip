@@ -12,7 +12,7 @@ namespace {
 
 // Streaming workgroups of the dot-product pass (as the context's default) and
 // the partials they publish: k values per workgroup, k <= 64.
-constexpr int kStaticGrid = 1024;
+constexpr int kStaticGrid = 512;
 constexpr int kStaticMaxK = 64;
 constexpr size_t kStaticPartials = (size_t)kStaticMaxK * kStaticGrid;
 // after the partials: c (64), scalars (S_COUNT) and the status word
@@ -20,7 +20,7 @@ constexpr size_t kStaticDoubles = kStaticPartials + kStaticMaxK + S_COUNT + 8;
 
 }  // namespace
 
-// One copy per GPU, held until the process ends (about 513 KiB).  Host code
+// One copy per GPU, held until the process ends (about 257 KiB).  Host code
 // never uses this name as an address: it asks for each device's address once.
 static __device__ __align__(256) double scratch[kStaticDoubles];
 
