@@ -666,11 +666,15 @@ def one_at_a_time(probs, ms, variant, tol, cap, check_every=10, flags=0):
     return out
 
 
-def batched_suite(variant, count, cap, train_count, train_iters, sample, lr=1e-3, fuse=0):
+def batched_suite(variant, count, cap, train_count, train_iters, sample, lr=1e-3, fuse=0,
+                  ablation_cap=600):
     """Batched AA on the 2D workload table (instance seeds 0..count-1):
     plain batched to tol 1e-8 (or the cap), the learned-guarded batch with a
     network trained on instances of disjoint seeds, and a seeded sample of
-    the same instances run one at a time through the single-instance path."""
+    the same instances run one at a time through the single-instance path;
+    the guard with the untrained network (what the training adds) to
+    ``ablation_cap`` iterations, beside the other two at that cap read from
+    their iteration counts."""
     import numpy as np
     import torch
     import aa_workloads as W
@@ -683,7 +687,7 @@ def batched_suite(variant, count, cap, train_count, train_iters, sample, lr=1e-3
     sum_n = sum(p.n for p in probs)
     stream = torch.cuda.Stream()
     res = {"instances": count, "sum_n": sum_n, "variant": variant, "tol": tol,
-           "max_iter": cap,
+           "max_iter": cap, "ablation_max_iter": min(cap, ablation_cap),
            "passes": ("RHS folded into QRAdd, QRDelete fused with its first pass"
                       if fuse == (aa.FUSE_RHS | aa.FUSE_DELETE) else
                       "separate" if fuse == 0 else f"flags {fuse}")}
@@ -716,7 +720,8 @@ def batched_suite(variant, count, cap, train_count, train_iters, sample, lr=1e-3
         # ablation: the same guard with the untrained network (delta gamma = 0,
         # beta = sigmoid(4)): what the training itself adds
         net0 = aa.AAMlp(count, seed=1, stream=stream)
-        untrained = batched_run(probs, ms, variant, tol, cap, 50, stream, net=net0, fuse=fuse)
+        untrained = batched_run(probs, ms, variant, tol, min(cap, ablation_cap), 50, stream,
+                                net=net0, fuse=fuse)
         print(f"# batched guarded, untrained network: {untrained['wall_s']:.1f} s",
               file=sys.stderr, flush=True)
     rng = np.random.default_rng(12345)
@@ -733,7 +738,10 @@ def batched_suite(variant, count, cap, train_count, train_iters, sample, lr=1e-3
         return {"wall_s": round(run["wall_s"], 3),
                 "steady_ms_per_iter": round(run["steady_ms_per_iter"], 3),
                 "converged": len(conv),
+                "converged_within_ablation_cap": int(sum(1 for s in conv
+                                                         if s.stop_iter <= ablation_cap)),
                 "median_iters_converged": float(np.median(its)),
+                "p90_iters_converged": float(np.percentile(its, 90)),
                 "g_evals_total": int(sum(s.g_evals for s in st)),
                 "accepted_total": int(sum(s.accepted for s in st))}
 
@@ -922,8 +930,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched / learned-guarded / one-at-a-time comparison")
     ap.add_argument("--batch-count", type=int, default=4096)
-    ap.add_argument("--batch-cap", type=int, default=600,
+    ap.add_argument("--batch-cap", type=int, default=5000,
                     help="iteration cap of the batched time-to-tolerance runs")
+    ap.add_argument("--ablation-cap", type=int, default=600,
+                    help="iteration cap of the untrained-network ablation")
     ap.add_argument("--train-count", type=int, default=4096)
     ap.add_argument("--train-iters", type=int, default=50)
     ap.add_argument("--single-sample", type=int, default=64,
@@ -1151,6 +1161,7 @@ def main():
     if not args.no_batch:
         batched = batched_suite(args.variant, args.batch_count, args.batch_cap, args.train_count,
                                 args.train_iters, args.single_sample,
+                                ablation_cap=args.ablation_cap,
                                 fuse=(aa.FUSE_RHS | aa.FUSE_DELETE)
                                 if args.batch_passes == "fused" else 0)
         batched["tail_largest_instances"] = batched_tail(
