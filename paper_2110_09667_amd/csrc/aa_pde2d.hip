@@ -19,12 +19,14 @@
 // kernel and 2 vector kernels; the whole working set at N = 1024 (~60 MB)
 // stays in the Infinity Cache, so the launches are latency bound.
 //
-// Reductions (r.z, p.q, r.r) end in the last workgroup to arrive (device-
-// scope fence and counter), which sums the per-workgroup partials in a fixed
-// order: deterministic, no separate finalize launch.  The stopping test runs
-// on the device at the start of each iteration; once it holds, every later
-// kernel returns at once, so the host may enqueue iterations ahead and read
-// the state only now and then.
+// Reductions (r.z, p.q, r.r): each workgroup stores its partial sum, and
+// every workgroup of the kernel that needs the value sums all partials itself
+// in one fixed order (the same value everywhere, deterministic).  No device-
+// scope fence (on gfx950 a release fence writes the whole L2 back: with one
+// per workgroup the vector kernels took 28 us instead of ~10) and no
+// finalize launch.  The stopping test runs on the device at the start of each
+// iteration; once it holds, every later kernel returns at once, so the host
+// may enqueue iterations ahead and read the state only now and then.
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -42,7 +44,9 @@ constexpr int kCoarseLds = 3 * (1024 + 256 + 64 + 16 + 4 + 1);
 constexpr int kMaxLevels = 32;
 
 // integer state words
-enum : int { I_DONE = 0, I_ITERS = 1, I_CONV = 2, I_COUNTER = 3, I_COUNT = 64 };
+enum : int { I_DONE = 0, I_ITERS = 1, I_CONV = 2, I_COUNT = 64 };
+// scalar slots: r.r of the right-hand side, rho of the previous iteration
+enum : int { S_RR0 = 0, S_RHO_PREV = 1, S_COUNT = 8 };
 
 struct Lev {
   int N;
@@ -54,18 +58,17 @@ struct Lev {
 };
 
 struct Pcg {
-  double* sc;        // [0] = r.r at k = 0; rr[k] = sc[1 + k]; rho[k]; pq[k]
-  int* ist;          // I_DONE, I_ITERS, I_CONV, I_COUNTER
-  double* partials;  // kMaxWG
-  int stride;        // max_iter + 2: length of each scalar history
+  double* sc;        // S_RR0, S_RHO_PREV
+  int* ist;          // I_DONE, I_ITERS, I_CONV
+  double* p_rr;      // partials of r.r (k_init, k_update), kMaxWG each
+  double* p_rho;     // partials of r.z (the cycle's last kernel on the fine grid)
+  double* p_pq;      // partials of p.q (k_dir)
+  int np_fine;       // partials of the fine-grid vector kernels (their workgroups)
+  int np_rho;        // partials of r.z: np_fine, or 1 from the coarse kernel
   double tol2;
   int max_iter;
   int fixed;         // >= 0: exactly this many iterations
 };
-
-__device__ __forceinline__ double* rr_at(const Pcg& a, int k) { return a.sc + 1 + k; }
-__device__ __forceinline__ double* rho_at(const Pcg& a, int k) { return a.sc + 1 + a.stride + k; }
-__device__ __forceinline__ double* pq_at(const Pcg& a, int k) { return a.sc + 1 + 2 * a.stride + k; }
 
 // --------------------------------------------------------------------------
 // point operations (shared by the grid-wide kernels and the LDS kernel)
@@ -166,8 +169,8 @@ __device__ __forceinline__ double post_red_point(const double* r, const double* 
 }
 
 // --------------------------------------------------------------------------
-// reductions: workgroup sum, then the last workgroup to arrive sums the
-// partials in workgroup order and stores the result
+// reductions: each workgroup stores its sum; the consumers add the partials
+// in index order (per thread, then the fixed tree of block_sum)
 // --------------------------------------------------------------------------
 
 __device__ double block_sum(double v, double* lds4) {
@@ -182,42 +185,36 @@ __device__ double block_sum(double v, double* lds4) {
   return s;
 }
 
-__device__ void reduce_store(double v, const Pcg& a, double* out) {
+// this workgroup's sum of v, stored as its partial
+__device__ void partial_store(double v, double* parts) {
   __shared__ double lds[16];
-  __shared__ int last;
   const double s = block_sum(v, lds);
-  const int nb = gridDim.x * gridDim.y;
-  const int b = blockIdx.y * gridDim.x + blockIdx.x;
-  if (threadIdx.x == 0) {
-    a.partials[b] = s;
-    __threadfence();
-    const unsigned t = atomicAdd(reinterpret_cast<unsigned*>(a.ist + I_COUNTER), 1u);
-    last = (t == (unsigned)nb - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
+  if (threadIdx.x == 0) parts[blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+// the sum of np partials, in one fixed order (every workgroup gets the same)
+__device__ double sum_parts(const double* parts, int np) {
+  __shared__ double lds[16];
   double acc = 0.0;
-  for (int k = threadIdx.x; k < nb; k += blockDim.x)
-    acc += __hip_atomic_load(a.partials + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const double tot = block_sum(acc, lds);
-  if (threadIdx.x == 0) {
-    *out = tot;
-    a.ist[I_COUNTER] = 0;
-  }
+  for (int k = threadIdx.x; k < np; k += blockDim.x) acc += parts[k];
+  return block_sum(acc, lds);
 }
 
 // The stopping test before iteration k (every workgroup decides alike; the
-// first records it).  Returns true when the solve has ended.
+// first records it, and at k = 0 keeps r.r of the right-hand side).  Returns
+// true when the solve has ended.
 __device__ __forceinline__ bool pcg_check(const Pcg& a, int k) {
   if (a.ist[I_DONE]) return true;
+  const double rr = sum_parts(a.p_rr, a.np_fine);
+  const double rr0 = k == 0 ? rr : a.sc[S_RR0];
+  if (k == 0 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) a.sc[S_RR0] = rr;
   bool stop;
   int conv;
   if (a.fixed >= 0) {
     stop = k >= a.fixed;
     conv = 1;
   } else {
-    conv = *rr_at(a, k) <= a.tol2 * a.sc[0];
+    conv = rr <= a.tol2 * rr0;
     stop = conv || k >= a.max_iter;
   }
   if (stop && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
@@ -267,7 +264,7 @@ __global__ __launch_bounds__(kBX) void k_post_red(Lev L, Pcg a, int k, int dot) 
     }
     if (dot) acc = fma(L.r[p], zv, acc);
   }
-  if (dot) reduce_store(acc, a, rho_at(a, k));
+  if (dot) partial_store(acc, a.p_rho);
 }
 
 // --------------------------------------------------------------------------
@@ -339,7 +336,7 @@ __global__ __launch_bounds__(kCoarseWG) void k_coarse(CoarseArgs c, Pcg a, int k
 #undef R_
 #undef E_
 #undef Z_
-  if (dot) reduce_store(acc, a, rho_at(a, k));
+  if (dot) partial_store(acc, a.p_rho);
 }
 
 // --------------------------------------------------------------------------
@@ -376,12 +373,8 @@ __global__ __launch_bounds__(kBX) void k_init(int problem, double lambda, const 
     a.ist[I_ITERS] = 0;
     a.ist[I_CONV] = 0;
   }
-  reduce_store(acc, a, a.sc);
+  partial_store(acc, a.p_rr);
 }
-
-// after the store of r.r at k = 0, copy it into rr[0] (the last workgroup of
-// k_init wrote sc[0]); one thread
-__global__ void k_rr0(Pcg a) { *rr_at(a, 0) = a.sc[0]; }
 
 // p = z + beta p_prev (beta = rho_k / rho_{k-1}; p = z at k = 0), q = A p, p.q
 __global__ __launch_bounds__(kBX) void k_dir(const double* z, const double* p_prev,
@@ -389,7 +382,8 @@ __global__ __launch_bounds__(kBX) void k_dir(const double* z, const double* p_pr
                                              int k) {
   if (a.ist[I_DONE]) return;
   const bool first = k == 0;
-  const double beta = first ? 0.0 : *rho_at(a, k) / *rho_at(a, k - 1);
+  const double rho = sum_parts(a.p_rho, a.np_rho);
+  const double beta = first ? 0.0 : rho / a.sc[S_RHO_PREV];
   double acc = 0.0;
   PDE_ROWS(N) PDE_COLS(N) {
     const int64_t p = (int64_t)j * N + i;
@@ -405,14 +399,17 @@ __global__ __launch_bounds__(kBX) void k_dir(const double* z, const double* p_pr
     q[p] = qv;
     acc = fma(pc, qv, acc);
   }
-  reduce_store(acc, a, pq_at(a, k));
+  partial_store(acc, a.p_pq);
 }
 
 // alpha = rho_k / (p.q); x += alpha p; r -= alpha q; r.r -> rr[k + 1]
 __global__ __launch_bounds__(kBX) void k_update(const double* p_cur, const double* q, double* x,
                                                 double* r, int N, Pcg a, int k) {
   if (a.ist[I_DONE]) return;
-  const double alpha = *rho_at(a, k) / *pq_at(a, k);
+  const double rho = sum_parts(a.p_rho, a.np_rho);
+  const double alpha = rho / sum_parts(a.p_pq, a.np_fine);
+  // rho_k for the next iteration's beta (k_dir read the previous one already)
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) a.sc[S_RHO_PREV] = rho;
   double acc = 0.0;
   PDE_ROWS(N) PDE_COLS(N) {
     const int64_t p = (int64_t)j * N + i;
@@ -421,7 +418,7 @@ __global__ __launch_bounds__(kBX) void k_update(const double* p_cur, const doubl
     r[p] = rv;
     acc = fma(rv, rv, acc);
   }
-  reduce_store(acc, a, rr_at(a, k + 1));
+  partial_store(acc, a.p_rr);
 }
 
 __global__ void k_reset(int* ist) {
@@ -448,7 +445,7 @@ struct aa_pde2d {
   hipStream_t st;
   int nlev, first_coarse;  // levels >= first_coarse run in k_coarse
   Lev lev[kMaxLevels];
-  double *r, *z, *e0, *p[2], *q, *sc, *partials;
+  double *r, *z, *e0, *p[2], *q, *sc, *p_rr, *p_rho, *p_pq;
   int* ist;
   int last_iters, last_conv, predicted;
 };
@@ -485,10 +482,12 @@ size_t layout(int64_t N, int max_iter, const int* sizes, int L, aa_pde2d* c, cha
     return p;
   };
   const size_t n = (size_t)N * (size_t)N;
+  (void)max_iter;
   int* ist = (int*)take(I_COUNT * sizeof(int));
-  const int stride = max_iter + 2;
-  double* sc = (double*)take((1 + 3 * (size_t)stride) * sizeof(double));
-  double* partials = (double*)take(kMaxWG * sizeof(double));
+  double* sc = (double*)take(S_COUNT * sizeof(double));
+  double* p_rr = (double*)take(kMaxWG * sizeof(double));
+  double* p_rho = (double*)take(kMaxWG * sizeof(double));
+  double* p_pq = (double*)take(kMaxWG * sizeof(double));
   double* r = (double*)take(n * 8);
   double* z = (double*)take(n * 8);
   double* e0 = (double*)take(n * 8);
@@ -498,7 +497,9 @@ size_t layout(int64_t N, int max_iter, const int* sizes, int L, aa_pde2d* c, cha
   if (c) {
     c->ist = ist;
     c->sc = sc;
-    c->partials = partials;
+    c->p_rr = p_rr;
+    c->p_rho = p_rho;
+    c->p_pq = p_pq;
     c->r = r;
     c->z = z;
     c->e0 = e0;
@@ -523,18 +524,6 @@ size_t layout(int64_t N, int max_iter, const int* sizes, int L, aa_pde2d* c, cha
   return off;
 }
 
-Pcg pcg_args(const aa_pde2d* c) {
-  Pcg a;
-  a.sc = c->sc;
-  a.ist = c->ist;
-  a.partials = c->partials;
-  a.stride = c->max_iter + 2;
-  a.tol2 = c->tol * c->tol;
-  a.max_iter = c->max_iter;
-  a.fixed = c->fixed;
-  return a;
-}
-
 dim3 grid_for(int N) {
   const int gx = (N + kBX - 1) / kBX;
   int gy = kMaxWG / gx;
@@ -546,6 +535,22 @@ dim3 grid_for(int N) {
 dim3 block_for(int N) {
   const int bx = N >= kBX ? kBX : ((N + 63) / 64) * 64;
   return dim3((unsigned)bx);
+}
+
+Pcg pcg_args(const aa_pde2d* c) {
+  Pcg a;
+  a.sc = c->sc;
+  a.ist = c->ist;
+  a.p_rr = c->p_rr;
+  a.p_rho = c->p_rho;
+  a.p_pq = c->p_pq;
+  const dim3 g = grid_for(c->N);
+  a.np_fine = (int)(g.x * g.y);
+  a.np_rho = c->first_coarse == 0 ? 1 : a.np_fine;  // r.z from the coarse kernel
+  a.tol2 = c->tol * c->tol;
+  a.max_iter = c->max_iter;
+  a.fixed = c->fixed;
+  return a;
 }
 
 // one V-cycle on r (level 0) into z; `check` runs the stopping test before
@@ -605,7 +610,6 @@ aa_status solve(aa_pde2d* c, int problem, const double* b, const double* u, doub
   const int N = c->N;
   hipLaunchKernelGGL(k_init, grid_for(N), block_for(N), 0, c->st, problem, c->lambda, b, u, x,
                      c->r, N, a);
-  hipLaunchKernelGGL(k_rr0, dim3(1), dim3(1), 0, c->st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return AA_EHIP;
   const int last = c->fixed >= 0 ? c->fixed : c->max_iter;
