@@ -3,8 +3,9 @@
 // 230 -> 256 -> 256 -> 256 -> 21 (padded to 256 in / 64 out), GELU (erf form),
 // BF16 operands on the matrix cores with FP32 accumulation, FP32 master
 // weights, Adam.  Everything is a dense contraction here, so every product is
-// one LDS-tiled v_mfma_f32_16x16x16bf16 GEMM (64 x 64 tile per workgroup,
-// one 16-row strip per wave); operand strides let the same kernel compute
+// one LDS-tiled GEMM on gfx950's v_mfma_f32_16x16x32_bf16 (64 x 64 tile per
+// workgroup, one 16-row strip per wave, K in steps of 32: half the MFMA
+// issues and LDS passes of the 16-deep form); operand strides let the same kernel compute
 // the forward products, the input gradients (times W^T) and the weight
 // gradients (H^T times dZ).  The network is small and latency-bound.
 #include <math.h>
@@ -18,7 +19,7 @@
 
 namespace aa {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 // float -> bfloat16 bits, round to nearest even (NaN kept quiet).
@@ -30,8 +31,9 @@ __device__ __forceinline__ uint16_t f2bf(float x) {
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-// Result layout of v_mfma_f32_16x16x16bf16_1k: lane l, register r holds
-// D[mfma_row(l, r)][l % 16].
+// Operand and result layout of v_mfma_f32_16x16x32_bf16: lane l supplies
+// A[l % 16][8 (l / 16) + e] and B[8 (l / 16) + e][l % 16], e < 8, and
+// register r of its result holds D[mfma_row(l, r)][l % 16].
 __device__ __forceinline__ int mfma_row(int lane, int r) { return 4 * (lane >> 4) + r; }
 
 struct GemmArgs {
@@ -44,12 +46,13 @@ struct GemmArgs {
 };
 
 constexpr int GT = 64;   // tile edge
-constexpr int GK = 16;   // K step of one MFMA
-constexpr int GKP = 20;  // LDS row stride (bf16 elements) of the K-major tiles
+constexpr int GK = 32;   // K step of one MFMA
+constexpr int GKP = 40;  // LDS row stride (bf16 elements) of the K-major tiles: 80 bytes,
+                         // 16-byte aligned rows for the 8-element operand reads
 
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
-  __shared__ uint16_t As[GT * GKP];  // [m][k]
-  __shared__ uint16_t Bs[GT * GKP];  // [n][k]
+  __shared__ __align__(16) uint16_t As[GT * GKP];  // [m][k]
+  __shared__ __align__(16) uint16_t Bs[GT * GKP];  // [n][k]
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
   v4f acc[4];
@@ -64,17 +67,13 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
       Bs[r * GKP + kk] = (n < g.N && k < g.K) ? g.b[k * g.sb0 + n * g.sb1] : (uint16_t)0;
     }
     __syncthreads();
-    v4s af;
-    const int ar = 16 * w + (lane & 15), ak = 4 * (lane >> 4);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) af[e] = (short)As[ar * GKP + ak + e];
+    const int ar = 16 * w + (lane & 15), ak = 8 * (lane >> 4);
+    const v8bf af = *reinterpret_cast<const v8bf*>(&As[ar * GKP + ak]);
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) {
-      v4s bfr;
       const int bn = 16 * nb + (lane & 15);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) bfr[e] = (short)Bs[bn * GKP + ak + e];
-      acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bfr, acc[nb], 0, 0, 0);
+      const v8bf bfr = *reinterpret_cast<const v8bf*>(&Bs[bn * GKP + ak]);
+      acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr, acc[nb], 0, 0, 0);
     }
     __syncthreads();
   }
