@@ -226,7 +226,10 @@ constexpr int kRotChSplit = AA_ROT_CH_SPLIT;
 // of a tile cannot overlap another wave's loads).  From na = 54 on the
 // half-staging kernel (eight waves) is faster: at n = 2^26, 63 columns,
 // 17.5 ms instead of 25.5; at 48-49 columns it is 10-17 % slower.
-constexpr int kGramSplitMin = 54;
+#ifndef AA_GRAM_SPLIT_MIN
+#define AA_GRAM_SPLIT_MIN 54
+#endif
+constexpr int kGramSplitMin = AA_GRAM_SPLIT_MIN;
 
 __host__ __device__ constexpr int gram_split_lds_doubles(int na) {
   return kWaves * 64 * kHalfStride > kWaves * (na * (na - 1) / 2)
