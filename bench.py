@@ -794,13 +794,16 @@ class Problem3D:
         self.omega = 0.9 / W.laplacian_lambda_max(3, s)
 
 
-def cpu_baseline(n=1 << 22, k=19, variant="icwy", reps=5):
+def cpu_baseline(n=1 << 22, k=19, variant="icwy", reps=5, c2_s=256, c2_m=20, c2_iters=3):
     """The oracle (its OpenMP build: fixed row blocks, bitwise the serial
     results) on a bounded sample of the headline measurement: QRAdds of a
     Gaussian column into a k-column basis at n = 2^22 (the GPU measures
     n = 2^26), each followed by an untimed QRDelete, median of ``reps`` at 1
     thread and at every host core; GB/s with the same byte model.  Also the
-    1D Poisson solves (1 thread)."""
+    1D Poisson solves (1 thread), and the 3D workload's AA iteration at the
+    GPU's size (s^3 grid, window c2_m) on every core: the window filled
+    (c2_m + 1 iterations, untimed), then ``c2_iters`` recycled iterations
+    timed (one core would take minutes)."""
     import numpy as np
 
     import aa_workloads as W
@@ -837,6 +840,21 @@ def cpu_baseline(n=1 << 22, k=19, variant="icwy", reps=5):
         _, _, r = O.run_aa(lambda z: O.G_stencil(p1, z), np.zeros(p1.n), 5, vv, 300, tol=1e-8,
                            record=False)
         poisson[vv] = {"iterations": len(r), "ms": round(1e3 * (time.perf_counter() - t1), 3)}
+    c2_threads = O.use_openmp(allc)
+    p3 = W.nonlinear3d(c2_s)
+    st = O.AA(p3.n, c2_m, variant)
+    x = np.zeros(p3.n)
+    for _ in range(c2_m + 1):
+        x = st.step(x, O.G_stencil(p3, x))
+    t0 = time.perf_counter()
+    for _ in range(c2_iters):
+        x = st.step(x, O.G_stencil(p3, x))
+    c2_ms = 1e3 * (time.perf_counter() - t0) / c2_iters
+    c2 = {"workload": f"3D nonlinear {c2_s}^3, {variant}, m = {c2_m}, window full",
+          "ms_per_iteration": round(c2_ms, 1), "threads": c2_threads,
+          "timed_iterations": c2_iters, "untimed_fill_iterations": c2_m + 1}
+    del st, x, p3
+    O.use_openmp(1)
     model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -850,10 +868,13 @@ def cpu_baseline(n=1 << 22, k=19, variant="icwy", reps=5):
     return {"value": round(gb_all, 3), "unit": "GB/s", "cores": used_all, "kind": "oracle",
             "one_core_value": round(gb_1, 3), "nproc": os.cpu_count(), "cpu_model": model,
             "poisson1d_to_1e-8_one_core": poisson,
+            "c2_iteration_all_cores": c2,
             "sample": (f"FP64 C oracle (OpenMP build, fixed row blocks): one {variant} QRAdd "
                        f"into a {k}-column basis at n = {n} (the GPU line is n = 2^26), "
                        f"median of {reps}: {dt_all:.2f} s on {used_all} threads, {dt_1:.2f} s "
-                       f"on 1")}
+                       f"on 1; and {c2_iters} recycled iterations of the 3D AA workload at "
+                       f"{c2_s}^3, m = {c2_m}, {c2_ms / 1e3:.2f} s each on {c2_threads} "
+                       f"threads")}
 
 
 def load_traffic(workload, kind):
@@ -1186,7 +1207,15 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(k=args.k, variant=args.variant)
+        cpu = cpu_baseline(k=args.k, variant=args.variant, c2_s=args.s, c2_m=args.m)
+        gpu_c2 = c2.get(args.variant)
+        if gpu_c2:
+            # the oracle's per-iteration time over the GPU's on the same
+            # iteration: the ratio of the two solves' times to tolerance, whose
+            # iteration counts agree (the host run itself would take hours)
+            cpu["c2_iteration_all_cores"]["gpu_ms_per_iteration"] = gpu_c2["ms_per_step"]
+            cpu["c2_iteration_all_cores"]["cpu_over_gpu"] = round(
+                cpu["c2_iteration_all_cores"]["ms_per_iteration"] / gpu_c2["ms_per_step"], 1)
 
     line = {
         "metric": METRIC,

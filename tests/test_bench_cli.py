@@ -32,6 +32,8 @@ def test_cpu_baseline_leg_runs_on_a_small_sample():
     column, since the delete drops the oldest one)."""
     sys.path.insert(0, ROOT)
     import bench
-    out = bench.cpu_baseline(n=1 << 12, k=5, reps=3)
+    out = bench.cpu_baseline(n=1 << 12, k=5, reps=3, c2_s=12, c2_m=4, c2_iters=2)
     assert out["kind"] == "oracle" and out["value"] > 0 and out["one_core_value"] > 0
     assert out["cores"] >= 1
+    c2 = out["c2_iteration_all_cores"]
+    assert c2["ms_per_iteration"] > 0 and c2["threads"] >= 1 and c2["timed_iterations"] == 2
