@@ -97,16 +97,10 @@ __device__ __forceinline__ f64x2 ld2v(const double2* p) {
 #endif
 }
 
-// AA_NT_STORE_ROT (default AA_STREAMING): the QRDelete rotation sweeps'
-// stores are non-temporal.
-#ifndef AA_NT_STORE_ROT
-#define AA_NT_STORE_ROT AA_STREAMING
-#endif
-
 // Store one 16-byte pair that no later pass of this call reads back soon
 // (non-temporal: the written columns far exceed the caches).
 __device__ __forceinline__ void st2v_stream(f64x2 v, double* p) {
-#if AA_NT_STORE_ROT
+#if AA_STREAMING
   __builtin_nontemporal_store(v, reinterpret_cast<f64x2*>(p));
 #else
   *reinterpret_cast<f64x2*>(p) = v;
@@ -115,7 +109,7 @@ __device__ __forceinline__ void st2v_stream(f64x2 v, double* p) {
 
 // Store one streamed value (the row-per-thread rotation sweep).
 __device__ __forceinline__ void st1_stream(double v, double* p) {
-#if AA_NT_STORE_ROT
+#if AA_STREAMING
   __builtin_nontemporal_store(v, p);
 #else
   *p = v;

@@ -740,9 +740,6 @@ constexpr int kRotCh = 8;
 #define AA_ROT_CH_PAIR 8
 #endif
 constexpr int kRotChPair = AA_ROT_CH_PAIR;
-#ifndef AA_ROT_PAIR
-#define AA_ROT_PAIR 1
-#endif
 
 // The first loads of a row's sweep (q_0 and the next CH columns), split off
 // so that a caller can issue them early (rotate_gram_body fetches the next
@@ -850,13 +847,8 @@ __device__ inline void rotate_body(const RotArgs& a, const double* s_c, const do
   const int64_t ntiles = (npair + kWG - 1) / kWG;
   for (int64_t tile = t0; tile < ntiles; tile += ts) {
     const int64_t row = 2 * (tile * kWG + threadIdx.x);
-    if (AA_ROT_PAIR && row + 1 < a.n)
+    if (row + 1 < a.n)
       rotate_pair<kRotChPair>(a, row, s_c, s_s);
-    else if (!AA_ROT_PAIR) {
-      const int64_t r1 = tile * 2 * kWG + threadIdx.x;
-      rotate_row(a, r1, r1 < a.n, s_c, s_s, [](int, double) {});
-      rotate_row(a, r1 + kWG, r1 + kWG < a.n, s_c, s_s, [](int, double) {});
-    }
     else if (row < a.n)
       rotate_row(a, row, true, s_c, s_s, [](int, double) {});
   }
