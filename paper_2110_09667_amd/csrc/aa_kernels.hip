@@ -142,6 +142,10 @@ __global__ __launch_bounds__(kWG) void k_update(UpdArgs a, Small sm) {
   publish(sm, update_nred(a), s_acc, 4);
 }
 
+// Column buckets up to AA_CGS2B_PAIR_MAX take the row-pair form.
+#ifndef AA_CGS2B_PAIR_MAX
+#define AA_CGS2B_PAIR_MAX 16
+#endif
 template <int KMAX>
 __global__ __launch_bounds__(kWG) void k_cgs2b(Cgs2bArgs a, Small sm) {
   if (aa_stopped(sm)) return;
@@ -150,7 +154,10 @@ __global__ __launch_bounds__(kWG) void k_cgs2b(Cgs2bArgs a, Small sm) {
   for (int j = threadIdx.x; j < KMAX; j += kWG) s_s[j] = (j < a.k) ? a.s[j] : 0.0;
   lds_zero(s_acc, kWaves * KMAX);
   __syncthreads();
-  cgs2b_body<KMAX>(a, s_s, blockIdx.x, gridDim.x, s_acc + (threadIdx.x >> 6) * KMAX);
+  if constexpr (KMAX <= AA_CGS2B_PAIR_MAX)
+    cgs2b_pair_body<KMAX>(a, s_s, blockIdx.x, gridDim.x, s_acc + (threadIdx.x >> 6) * KMAX);
+  else
+    cgs2b_body<KMAX>(a, s_s, blockIdx.x, gridDim.x, s_acc + (threadIdx.x >> 6) * KMAX);
   publish(sm, a.k, s_acc, KMAX);
 }
 

@@ -584,6 +584,45 @@ __device__ inline void cgs2b_body(const Cgs2bArgs& a, const double* s_s, int64_t
   }
 }
 
+// The grid pass for few columns (k <= KMAX, KMAX small): 16-byte row pairs
+// and per-lane running sums with one KMAX-wide butterfly per wave at the
+// end.  The one-row form above reduces every 256-row tile, which leaves too
+// little in flight when k is small (k = 1 streamed 1.9 TB/s).
+template <int KMAX>
+__device__ inline void cgs2b_pair_body(const Cgs2bArgs& a, const double* s_s, int64_t t0,
+                                       int64_t ts, double* acc) {
+  const int lane = threadIdx.x & 63;
+  double sum[KMAX];
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) sum[j] = 0.0;
+  for_tiles(a.n, t0, ts, [&](int64_t b2, auto full) {
+    constexpr bool F = decltype(full)::value;
+    double2 q[KMAX][kPairs];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+      if (j < a.k) ld2<F>(q[j], a.Q + (int64_t)j * a.ldq, b2, a.n);
+      else zero2(q[j]);
+    }
+    double2 y[kPairs];
+    ld2<F>(y, a.v, b2, a.n);
+#pragma unroll
+    for (int i = 0; i < kPairs; ++i) {
+      double sx = 0.0, sy = 0.0;
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j) {
+        sx = fma(q[j][i].x, s_s[j], sx);
+        sy = fma(q[j][i].y, s_s[j], sy);
+      }
+      y[i].x -= sx;
+      y[i].y -= sy;
+    }
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) sum[j] += dot2(q[j], y);
+  });
+  const double r = multi_reduce<KMAX>(sum);
+  if (lane < KMAX && lane < a.k) acc[lane] += r;
+}
+
 // The same pass with per-lane running sums (workgroup-level step, at most
 // KMAX columns): per row the same y = v - Q s, then sum_j += q_j y over all of
 // the lane's rows, and one KMAX-wide butterfly per wave at the end instead of
