@@ -142,9 +142,10 @@ __global__ __launch_bounds__(kWG) void k_update(UpdArgs a, Small sm) {
   publish(sm, update_nred(a), s_acc, 4);
 }
 
-// Column buckets up to AA_CGS2B_PAIR_MAX take the row-pair form.
+// Column buckets up to AA_CGS2B_PAIR_MAX take the row-pair form (32: the
+// 32-column bucket too, with one pair per lane).
 #ifndef AA_CGS2B_PAIR_MAX
-#define AA_CGS2B_PAIR_MAX 16
+#define AA_CGS2B_PAIR_MAX 32
 #endif
 template <int KMAX>
 __global__ __launch_bounds__(kWG) void k_cgs2b(Cgs2bArgs a, Small sm) {
@@ -155,7 +156,8 @@ __global__ __launch_bounds__(kWG) void k_cgs2b(Cgs2bArgs a, Small sm) {
   lds_zero(s_acc, kWaves * KMAX);
   __syncthreads();
   if constexpr (KMAX <= AA_CGS2B_PAIR_MAX)
-    cgs2b_pair_body<KMAX>(a, s_s, blockIdx.x, gridDim.x, s_acc + (threadIdx.x >> 6) * KMAX);
+    cgs2b_pair_body<KMAX, (KMAX <= 16 ? kPairs : 1)>(a, s_s, blockIdx.x, gridDim.x,
+                                                     s_acc + (threadIdx.x >> 6) * KMAX);
   else
     cgs2b_body<KMAX>(a, s_s, blockIdx.x, gridDim.x, s_acc + (threadIdx.x >> 6) * KMAX);
   publish(sm, a.k, s_acc, KMAX);

@@ -584,29 +584,52 @@ __device__ inline void cgs2b_body(const Cgs2bArgs& a, const double* s_s, int64_t
   }
 }
 
-// The grid pass for few columns (k <= KMAX, KMAX small): 16-byte row pairs
-// and per-lane running sums with one KMAX-wide butterfly per wave at the
-// end.  The one-row form above reduces every 256-row tile, which leaves too
-// little in flight when k is small (k = 1 streamed 1.9 TB/s).
-template <int KMAX>
+// The grid pass for at most KMAX columns on 16-byte row pairs (NP per lane
+// per tile) with per-lane running sums and one KMAX-wide butterfly per wave
+// at the end.  The one-row form above reduces every 256-row tile, which
+// leaves too little in flight when k is small (k = 1 streamed 1.9 TB/s).
+// The 32-column bucket takes one pair per lane (its 32 column pairs already
+// keep 512 bytes per lane in flight, and two would not fit the registers).
+template <bool FULL, int NP>
+__device__ __forceinline__ void ld2n(double2 (&r)[NP], const double* __restrict__ p, int64_t b2,
+                                     int64_t n) {
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const int64_t row = b2 + (int64_t)i * 2 * kWG;
+    if (FULL) {
+      const f64x2 v = ld2v(reinterpret_cast<const double2*>(p + row));
+      r[i] = make_double2(v.x, v.y);
+    } else {
+      r[i].x = row < n ? p[row] : 0.0;
+      r[i].y = row + 1 < n ? p[row + 1] : 0.0;
+    }
+  }
+}
+
+template <int KMAX, int NP>
 __device__ inline void cgs2b_pair_body(const Cgs2bArgs& a, const double* s_s, int64_t t0,
                                        int64_t ts, double* acc) {
   const int lane = threadIdx.x & 63;
+  constexpr int64_t kRows = (int64_t)kWG * 2 * NP;  // rows per tile
   double sum[KMAX];
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) sum[j] = 0.0;
-  for_tiles(a.n, t0, ts, [&](int64_t b2, auto full) {
+  auto body = [&](int64_t b2, auto full) {
     constexpr bool F = decltype(full)::value;
-    double2 q[KMAX][kPairs];
+    double2 q[KMAX][NP];
 #pragma unroll
     for (int j = 0; j < KMAX; ++j) {
-      if (j < a.k) ld2<F>(q[j], a.Q + (int64_t)j * a.ldq, b2, a.n);
-      else zero2(q[j]);
-    }
-    double2 y[kPairs];
-    ld2<F>(y, a.v, b2, a.n);
+      if (j < a.k) {
+        ld2n<F, NP>(q[j], a.Q + (int64_t)j * a.ldq, b2, a.n);
+      } else {
 #pragma unroll
-    for (int i = 0; i < kPairs; ++i) {
+        for (int i = 0; i < NP; ++i) q[j][i] = make_double2(0.0, 0.0);
+      }
+    }
+    double2 y[NP];
+    ld2n<F, NP>(y, a.v, b2, a.n);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
       double sx = 0.0, sy = 0.0;
 #pragma unroll
       for (int j = 0; j < KMAX; ++j) {
@@ -617,8 +640,24 @@ __device__ inline void cgs2b_pair_body(const Cgs2bArgs& a, const double* s_s, in
       y[i].y -= sy;
     }
 #pragma unroll
-    for (int j = 0; j < KMAX; ++j) sum[j] += dot2(q[j], y);
-  });
+    for (int j = 0; j < KMAX; ++j) {
+      double d = 0.0;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        d = fma(q[j][i].x, y[i].x, d);
+        d = fma(q[j][i].y, y[i].y, d);
+      }
+      sum[j] += d;
+    }
+  };
+  const int64_t ntiles = (a.n + kRows - 1) / kRows;
+  for (int64_t tile = t0; tile < ntiles; tile += ts) {
+    const int64_t b2 = tile * kRows + 2 * (int64_t)threadIdx.x;
+    if ((tile + 1) * kRows <= a.n)
+      body(b2, std::true_type{});
+    else
+      body(b2, std::false_type{});
+  }
   const double r = multi_reduce<KMAX>(sum);
   if (lane < KMAX && lane < a.k) acc[lane] += r;
 }
