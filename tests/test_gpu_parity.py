@@ -527,15 +527,20 @@ def test_icwy_step_keeps_T_invariant(m):
     assert checked == 3 and ctx.info().status == 0
 
 
+@pytest.mark.parametrize("k", [8, 19])
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_qr_add_microbenchmark_size_properties(variant):
-    """n = 2^26 (the QRAdd microbenchmark size): build 8 orthonormal columns
-    with the library, add one Gaussian column, check Q^T q_new = 0 and
-    Q R_{:,k} = v with torch FP64 products."""
+def test_qr_add_microbenchmark_size_properties(variant, k):
+    """n = 2^26 (the QRAdd microbenchmark size; k = 19 is the headline add,
+    the 32-column kernels): build k orthonormal columns with the library, add
+    one Gaussian column, check Q^T q_new = 0 and Q R_{:,k} = v with torch
+    FP64 products; then QRDelete (the rotation pass, with ICWY's Gram) and
+    check that the k rotated columns stay orthonormal, R stays upper
+    triangular, and (ICWY) the refreshed T holds the strictly lower part of
+    the rotated basis's Q^T Q under a unit diagonal."""
     import torch
     device()
     aa = aa_mod()
-    n, k = 1 << 26, 8
+    n = 1 << 26
     ctx = aa.AAContext(n, k + 1, variant, aa.QR_ONLY)
     v = torch.empty(n, dtype=torch.float64, device="cuda")
     for j in range(k + 1):
@@ -550,6 +555,20 @@ def test_qr_add_microbenchmark_size_properties(variant):
     assert abs(torch.dot(qn, qn).item() - 1.0) <= 1e-13
     recon = Q @ R[:, k]
     assert (torch.linalg.norm(recon - v) / torch.linalg.norm(v)).item() <= 1e-13
+    del Q, qn, recon
+    ctx.qr_delete()
+    assert ctx.info().status == 0
+    Rk, Tk, kk = ctx.get_qr()
+    assert kk == k
+    Qd = ctx.basis(k)
+    gram = (Qd.T @ Qd).cpu().numpy()
+    assert np.abs(gram - np.eye(k)).max() <= 1e-12
+    assert np.all(np.tril(Rk[:k, :k], -1) == 0.0)
+    if variant == "icwy":
+        # the refreshed T: unit diagonal, strictly lower part = that of Q^T Q
+        assert np.all(np.diag(Tk[:k, :k]) == 1.0)
+        assert np.abs(np.tril(Tk[:k, :k], -1) - np.tril(gram, -1)).max() <= 1e-14
+    ctx.close()
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
