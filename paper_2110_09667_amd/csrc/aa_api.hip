@@ -253,6 +253,7 @@ aa_status qr_add_impl(aa_ctx* c, const double* v, const double* f = nullptr,
         for (int j = 1; j < k; ++j) {
           UpdArgs uj = u;
           uj.v = cur; uj.out = c->W; uj.j0 = j - 1; uj.nc = 1; uj.c1 = Rcol; uj.dotcol = j;
+          uj.rev = (j & 1);  // alternate with the previous pass (dots: forward)
           Tail tj = tail(TAIL_MGS_R, k);
           tj.row = j;
           chk(timed(c, AA_K_UPDATE, 4, [&] { return launch_update(uj, c->sm, tj, G, st); }));
@@ -260,6 +261,7 @@ aa_status qr_add_impl(aa_ctx* c, const double* v, const double* f = nullptr,
         }
         UpdArgs uk = u;
         uk.v = cur; uk.out = slotk; uk.j0 = k - 1; uk.nc = 1; uk.c1 = Rcol; uk.nrm = 1;
+        uk.rev = (k & 1);
         chk(timed(c, AA_K_UPDATE, 3, [&] { return launch_update(uk, c->sm, tn, G, st); }));
         c->syncs_add += k + 1;
         break;
@@ -281,6 +283,7 @@ aa_status qr_add_impl(aa_ctx* c, const double* v, const double* f = nullptr,
         UpdArgs uc = u;
         uc.v = v; uc.out = slotk; uc.j0 = 0; uc.nc = k; uc.c1 = c->sm.coef0; uc.c2 = c->sm.coef1;
         uc.nrm = 1;
+        uc.rev = 1;  // after a forward pass over the same columns
         if (fuse) {
           uc.rhsv = f;
           tn.rhs = 1;
@@ -303,6 +306,7 @@ aa_status qr_add_impl(aa_ctx* c, const double* v, const double* f = nullptr,
                     [&] { return launch_dots(d, c->sm, ti, G, st); }));
         UpdArgs ub = u;
         ub.v = v; ub.out = slotk; ub.j0 = 0; ub.nc = k; ub.c1 = c->sm.coef0; ub.nrm = 1;
+        ub.rev = 1;  // after a forward pass over the same columns
         if (fuse) {
           ub.rhsv = f;
           tn.rhs = 1;
@@ -328,6 +332,7 @@ aa_status qr_add_impl(aa_ctx* c, const double* v, const double* f = nullptr,
           chk(timed(c, AA_K_DOTS, k + 1 + zf, [&] { return launch_dots(d, c->sm, ta, G, st); }));
         UpdArgs ub = u;
         ub.v = v; ub.out = slotk; ub.c1 = Rcol; ub.nrm = 1;
+        ub.rev = 1;  // after a forward pass over the same columns
         if (fuse) {
           ub.rhsv = f;
           tn.rhs = 1;
@@ -363,6 +368,7 @@ aa_status qr_add_impl(aa_ctx* c, const double* v, const double* f = nullptr,
         ub.v = v; ub.out = slotk; ub.c1 = c->sm.coef0; ub.s = c->sm.coef1;
         ub.dcgs2_p = p; ub.reorth = 1; ub.j0 = 0; ub.nc = p;
         ub.pdiv = c->sm.scal + S_RHO; ub.odiv = c->sm.scal + S_RKK;
+        ub.rev = 1;  // after a forward pass over the same columns
         chk(timed(c, AA_K_UPDATE, k + 3, [&] { return launch_update(ub, c->sm, tail(TAIL_NONE, k), G, st); }));
         c->syncs_add += 1;
         if (e != hipSuccess) return AA_EHIP;

@@ -146,6 +146,10 @@ struct UpdArgs {
   // output by *odiv (device scalars; null: no division)
   const double* pdiv;
   const double* odiv;
+  // 1: walk the row tiles from the last to the first.  A pass that follows
+  // another over the same columns runs the other way, so its first tiles are
+  // the previous pass's last ones, still in the Infinity Cache.
+  int rev;
 };
 
 struct Cgs2bArgs {       // y = v - Q s (registers), red[j] = Q_j^T y

@@ -263,6 +263,22 @@ __device__ __forceinline__ void for_tiles(int64_t n, int64_t t0, int64_t ts, Bod
   }
 }
 
+// for_tiles, optionally from the last tile to the first (the same tiles per
+// workgroup position, mirrored).
+template <class Body>
+__device__ __forceinline__ void for_tiles_dir(int64_t n, int64_t t0, int64_t ts, bool rev,
+                                              Body&& body) {
+  const int64_t ntiles = (n + kTile - 1) / kTile;
+  for (int64_t it = t0; it < ntiles; it += ts) {
+    const int64_t tile = rev ? ntiles - 1 - it : it;
+    const int64_t b2 = tile * kTile + 2 * (int64_t)threadIdx.x;
+    if ((tile + 1) * kTile <= n)
+      body(b2, std::true_type{});
+    else
+      body(b2, std::false_type{});
+  }
+}
+
 __device__ __forceinline__ void lds_zero(double* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
 }
@@ -483,7 +499,7 @@ __device__ inline void update_body(const UpdArgs& a, const double* s_c1, const d
   const double* c2 = a.c2 ? s_c2 : nullptr;
   const double pdv = a.pdiv ? *a.pdiv : 1.0, odv = a.odiv ? *a.odiv : 1.0;
   double sdot = 0.0, snrm = 0.0, srhs = 0.0;  // this lane's running sums
-  for_tiles(a.n, t0, ts, [&](int64_t b2, auto full) {
+  for_tiles_dir(a.n, t0, ts, a.rev != 0, [&](int64_t b2, auto full) {
     constexpr bool F = decltype(full)::value;
     double2 o[kPairs], dq[kPairs], acc1[kPairs], acc2[kPairs];
     ld2<F>(o, a.v, b2, a.n);
