@@ -173,13 +173,25 @@ __global__ __launch_bounds__(64) void k_givens(Small sm, int k, int transform) {
   }
 }
 
+template <int CH>
 __global__ __launch_bounds__(kWG) void k_rotate(RotArgs a, Small sm) {
   if (aa_stopped(sm)) return;
   __shared__ double s_c[kMaxCols], s_s[kMaxCols];
   givens_coefs(a, sm.cap, s_c, s_s, kMaxCols);
   __syncthreads();
-  rotate_body(a, s_c, s_s, blockIdx.x, gridDim.x);
+  rotate_body<CH>(a, s_c, s_s, blockIdx.x, gridDim.x);
 }
+
+// Load depth of the plain rotation for long columns (n >= AA_ROT_LONG_N): at
+// n = 2^25 and 2^26 four column pairs in flight per lane streamed 5-9 %
+// faster than eight for k >= 19 (about the same at k = 9); at n = 2^24 eight
+// were faster at k = 19.
+#ifndef AA_ROT_LONG_N
+#define AA_ROT_LONG_N (1ll << 25)
+#endif
+#ifndef AA_ROT_CH_LONG
+#define AA_ROT_CH_LONG 4
+#endif
 
 // WAVES waves per workgroup: wide Gram staging (KMAX = 64 needs 25 KiB per
 // wave) uses two-wave workgroups so that three of them share a compute unit
@@ -679,7 +691,10 @@ hipError_t launch_rotate(const RotArgs& a, const Small& sm, const Tail& t, int g
     }
     return launch_finalize(sm, t, na * (na - 1) / 2, grid, st);
   }
-  hipLaunchKernelGGL(k_rotate, dim3(grid), dim3(kWG), 0, st, a, sm);
+  if (a.n >= AA_ROT_LONG_N)
+    hipLaunchKernelGGL(k_rotate<AA_ROT_CH_LONG>, dim3(grid), dim3(kWG), 0, st, a, sm);
+  else
+    hipLaunchKernelGGL(k_rotate<kRotChPair>, dim3(grid), dim3(kWG), 0, st, a, sm);
   return hipGetLastError();
 }
 

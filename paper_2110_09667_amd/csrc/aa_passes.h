@@ -935,6 +935,8 @@ __device__ __forceinline__ void rotate_pair(const RotArgs& a, int64_t row, const
 }
 
 // Row pairs p = tile kWG + tid (rows 2p, 2p + 1); an odd last row alone.
+// CH: load depth of the paired sweep.
+template <int CH = kRotChPair>
 __device__ inline void rotate_body(const RotArgs& a, const double* s_c, const double* s_s,
                                    int64_t t0, int64_t ts) {
   const int64_t npair = (a.n + 1) / 2;
@@ -942,7 +944,7 @@ __device__ inline void rotate_body(const RotArgs& a, const double* s_c, const do
   for (int64_t tile = t0; tile < ntiles; tile += ts) {
     const int64_t row = 2 * (tile * kWG + threadIdx.x);
     if (row + 1 < a.n)
-      rotate_pair<kRotChPair>(a, row, s_c, s_s);
+      rotate_pair<CH>(a, row, s_c, s_s);
     else if (row < a.n)
       rotate_row(a, row, true, s_c, s_s, [](int, double) {});
   }
