@@ -276,14 +276,16 @@ aa_status qr_add_impl(aa_ctx* c, const double* v, const double* f = nullptr,
         if (!first_done)
           chk(timed(c, AA_K_DOTS, k + 1 + zf,
                     [&] { return launch_dots(d, c->sm, ts, G, st); }));
-        Cgs2bArgs b{c->Q, c->ldq, c->n, v, k, c->sm.coef0};
+        // the three passes alternate direction: dots forward, this pass
+        // backward, the update forward
+        Cgs2bArgs b{c->Q, c->ldq, c->n, v, k, c->sm.coef0, 1};
         const int Gb = grid_rows(c, c->grid_stream_max);
         chk(timed(c, AA_K_CGS2B, k + 1,
                   [&] { return launch_cgs2b(b, c->sm, tail(TAIL_CGS2_Z, k), Gb, st); }));
         UpdArgs uc = u;
         uc.v = v; uc.out = slotk; uc.j0 = 0; uc.nc = k; uc.c1 = c->sm.coef0; uc.c2 = c->sm.coef1;
         uc.nrm = 1;
-        uc.rev = 1;  // after a forward pass over the same columns
+        uc.rev = 0;  // after the backward second pass
         if (fuse) {
           uc.rhsv = f;
           tn.rhs = 1;

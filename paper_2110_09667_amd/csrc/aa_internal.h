@@ -156,6 +156,7 @@ struct Cgs2bArgs {       // y = v - Q s (registers), red[j] = Q_j^T y
   const double* Q; int64_t ldq; int64_t n;
   const double* v; int k;
   const double* s;
+  int rev;               // 1: row tiles last to first (as UpdArgs::rev)
 };
 
 struct RotArgs {         // Givens sweep over k columns (+ ICWY Gram of k-1)

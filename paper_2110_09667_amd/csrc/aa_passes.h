@@ -582,7 +582,8 @@ __device__ inline void cgs2b_body(const Cgs2bArgs& a, const double* s_s, int64_t
                                   double* acc) {
   const int lane = threadIdx.x & 63;
   const int64_t ntiles = (a.n + kWG - 1) / kWG;
-  for (int64_t tile = t0; tile < ntiles; tile += ts) {
+  for (int64_t it = t0; it < ntiles; it += ts) {
+    const int64_t tile = a.rev ? ntiles - 1 - it : it;
     const int64_t row = tile * kWG + threadIdx.x;
     const bool valid = row < a.n;
     double q[KMAX];
@@ -667,7 +668,8 @@ __device__ inline void cgs2b_pair_body(const Cgs2bArgs& a, const double* s_s, in
     }
   };
   const int64_t ntiles = (a.n + kRows - 1) / kRows;
-  for (int64_t tile = t0; tile < ntiles; tile += ts) {
+  for (int64_t it = t0; it < ntiles; it += ts) {
+    const int64_t tile = a.rev ? ntiles - 1 - it : it;
     const int64_t b2 = tile * kRows + 2 * (int64_t)threadIdx.x;
     if ((tile + 1) * kRows <= a.n)
       body(b2, std::true_type{});
