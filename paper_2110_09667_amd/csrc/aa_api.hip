@@ -613,6 +613,7 @@ aa_ctx* view_create(const BInst& I, int variant, unsigned flags, double* partial
   c->g_prev = I.g_prev;
   c->sm = I.sm;
   c->sm.partials = partials;
+  c->sm.npart = 0;  // the split path's buffer: sums in the finalize
   c->sm.stop = nullptr;
   c->stop_dev = stop;
   c->one_wg_ok = false;
@@ -693,6 +694,7 @@ aa_status aa_init(aa_ctx** ctx, int64_t n, int m, int variant, unsigned flags,
   c->sm.scal = (double*)(base + L.off_scal);
   c->sm.status = (int*)(base + L.off_status);
   c->sm.partials = (double*)(base + L.off_part);
+  c->sm.npart = (int64_t)kPartials;
   c->sm.cap = m;
   c->sm.stop = nullptr;  // set only while an AA step is enqueued
   c->stop_dev = (StopState*)(base + L.off_stop);

@@ -73,6 +73,8 @@ struct Small {
   int* status;      // latched aa_status
   double* partials; // reduction partials, [nred][grid]
   int cap;
+  int64_t npart;    // doubles the partials buffer holds (0: not stated; the
+                    // finalize then sums the partials in one workgroup)
   // AA step launches only (null otherwise): once done is set or a breakdown
   // is latched in status, every kernel of the step returns at once, and the
   // x update writes x_next = x (or G(x) in the step that broke down)

@@ -50,7 +50,22 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int
 
 // Fixed-order sum of the G partials of each of the nred values (one wave per
 // value, two values per wave in flight), then the dense tail.
-__global__ __launch_bounds__(kFinWG) void k_finalize(Small sm, Tail t, int nred, int G) {
+// Sums of the G partials of each value, one wave per value in the same fixed
+// order as k_finalize's (bitwise the same sums), stored after the partials
+// at partials[nred * G + c].  For the wide ICWY Gram (over a thousand values
+// from hundreds of workgroups: 6.9 MB at m = 50) one workgroup reading them
+// alone took 156 us.
+__global__ __launch_bounds__(kWG) void k_sum_partials(Small sm, int nred, int G) {
+  if (aa_stopped(sm)) return;
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (c >= nred) return;
+  const double s = sum_partials(sm.partials + (size_t)c * G, G, lane);
+  if (lane == 0) sm.partials[(size_t)nred * G + c] = s;
+}
+
+// pre: the sums were formed by k_sum_partials.
+__global__ __launch_bounds__(kFinWG) void k_finalize(Small sm, Tail t, int nred, int G, int pre) {
   __shared__ double red[kMaxRedAll];
   if (sm.stop) {
     // the x update's finalize ends an iteration that broke down (its x update
@@ -65,13 +80,17 @@ __global__ __launch_bounds__(kFinWG) void k_finalize(Small sm, Tail t, int nred,
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   constexpr int waves = kFinWG / 64;
-  for (int c = w; c < nred; c += 2 * waves) {
-    const int c2 = c + waves;
-    const double s1 = sum_partials(sm.partials + (size_t)c * G, G, lane);
-    const double s2 = c2 < nred ? sum_partials(sm.partials + (size_t)c2 * G, G, lane) : 0.0;
-    if (lane == 0) {
-      red[c] = s1;
-      if (c2 < nred) red[c2] = s2;
+  if (pre) {
+    for (int c = threadIdx.x; c < nred; c += kFinWG) red[c] = sm.partials[(size_t)nred * G + c];
+  } else {
+    for (int c = w; c < nred; c += 2 * waves) {
+      const int c2 = c + waves;
+      const double s1 = sum_partials(sm.partials + (size_t)c * G, G, lane);
+      const double s2 = c2 < nred ? sum_partials(sm.partials + (size_t)c2 * G, G, lane) : 0.0;
+      if (lane == 0) {
+        red[c] = s1;
+        if (c2 < nred) red[c2] = s2;
+      }
     }
   }
   __syncthreads();
@@ -529,6 +548,13 @@ static int clamp_resident(int grid, const void* kernel, int threads, size_t lds)
   return (r > 0 && grid > r) ? r : grid;
 }
 
+// Partials (values x workgroups) from which the sums run on one wave per
+// value before the finalize.
+#ifndef AA_SUM_PARTIALS_MIN
+#define AA_SUM_PARTIALS_MIN 65536
+#endif
+constexpr int64_t kSumPartialsMin = AA_SUM_PARTIALS_MIN;
+
 static hipError_t launch_finalize(const Small& sm, const Tail& t, int nred, int grid,
                                   hipStream_t st) {
   hipError_t e = hipGetLastError();
@@ -538,7 +564,13 @@ static hipError_t launch_finalize(const Small& sm, const Tail& t, int nred, int 
     if (e != hipSuccess) return e;
     t_prof_mid_used = true;
   }
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinWG), 0, st, sm, t, nred, grid);
+  // many partials (the wide Gram): sum them with one wave per value first
+  const int64_t many = (int64_t)nred * grid;
+  const int pre = many >= kSumPartialsMin && sm.npart >= many + nred ? 1 : 0;
+  if (pre)
+    hipLaunchKernelGGL(k_sum_partials, dim3((nred + kWaves - 1) / kWaves), dim3(kWG), 0, st, sm,
+                       nred, grid);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinWG), 0, st, sm, t, nred, grid, pre);
   return hipGetLastError();
 }
 
